@@ -1,0 +1,271 @@
+"""CPU FP64 oracle for the grid-embedded BEM operator (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+and never imports it.
+
+The arithmetic lives in ``bem_oracle.c`` (plain C, FP64, OpenMP over targets):
+a direct O(M^2) summation of the discrete operator that the FFT convolution of
+the paper (Sec. 3, eqs. 14-16) evaluates.  This module only marshals arrays and
+adds two textbook steps on top: a dense LU solve of the assembled system
+(``numpy.linalg.solve``) and a plain restarted GMRES written from its
+definition, for the mixed boundary-value problem of eq. (4)/(8).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bem_oracle.c")
+_LIB = os.path.join(_HERE, "libbem_oracle.so")
+
+LAPLACE2D, LAPLACE3D, NAVIER3D = 0, 1, 2
+C_HALF, C_USER, C_IMPLICIT = 0, 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lp = ctypes.POINTER(ctypes.c_long)
+        L.orc_laplace2d.argtypes = [dp, dp]
+        L.orc_laplace3d.argtypes = [dp, dp]
+        L.orc_kelvin_u.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_kelvin_t.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_self_laplace2d.argtypes = [ctypes.c_double]
+        L.orc_self_laplace2d.restype = ctypes.c_double
+        L.orc_self_laplace3d.argtypes = [ctypes.c_double]
+        L.orc_self_laplace3d.restype = ctypes.c_double
+        L.orc_self_kelvin.argtypes = [ctypes.c_double, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_grid_k0.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_snap.argtypes = [ctypes.c_int, ctypes.c_long, dp, ctypes.c_double, dp, lp, lp]
+        L.orc_snap.restype = ctypes.c_long
+        L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_long, lp, dp, dp, ctypes.c_int, dp, dp, dp,
+                                ctypes.c_long, ctypes.c_long, dp, dp, dp]
+        L.orc_assemble.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_long, lp, dp, dp, dp, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _l(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# ----------------------------------------------------------------- kernels
+
+
+def laplace2d(xi):
+    """(u*, du*/dx, du*/dy) at displacement xi = field - target, eqs. (3), (12)."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_laplace2d(_d(xi), _d(out))
+    return out
+
+
+def laplace3d(xi):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    out = np.zeros(4)
+    lib().orc_laplace3d(_d(xi), _d(out))
+    return out
+
+
+def kelvin_u(xi, nu, mu):
+    """Kelvin displacement tensor of eq. (7), 3x3."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    out = np.zeros(9)
+    lib().orc_kelvin_u(_d(xi), nu, mu, _d(out))
+    return out.reshape(3, 3)
+
+
+def kelvin_t(xi, n, nu):
+    """Kelvin traction kernel T[k, j] (force direction k, component j)."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.zeros(9)
+    lib().orc_kelvin_t(_d(xi), _d(n), nu, _d(out))
+    return out.reshape(3, 3)
+
+
+def self_laplace2d(w):
+    return float(lib().orc_self_laplace2d(float(w)))
+
+
+def self_laplace3d(w):
+    return float(lib().orc_self_laplace3d(float(w)))
+
+
+def self_kelvin(w, n, nu, mu):
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.zeros(9)
+    lib().orc_self_kelvin(float(w), _d(n), nu, mu, _d(out))
+    return out.reshape(3, 3)
+
+
+def grid_k0(kernel, h, nu=0.3, mu=1.0):
+    out = np.zeros(9)
+    lib().orc_grid_k0(kernel, h, nu, mu, _d(out))
+    return out.reshape(3, 3)
+
+
+# ----------------------------------------------------------------- operator
+
+
+@dataclass
+class Problem:
+    """Geometry handed to the oracle: plain arrays, nothing else."""
+
+    kernel: int
+    h: float
+    origin: np.ndarray
+    n: np.ndarray
+    nodes: np.ndarray
+    normals: np.ndarray
+    weights: np.ndarray
+    nu: float = 0.3
+    mu: float = 1.0
+
+    @property
+    def dim(self):
+        return 2 if self.kernel == LAPLACE2D else 3
+
+    @property
+    def ncomp(self):
+        return 3 if self.kernel == NAVIER3D else 1
+
+    @property
+    def m(self):
+        return int(self.weights.shape[0])
+
+
+def problem(geom, kernel, nu=0.3, mu=1.0) -> Problem:
+    """Build an oracle Problem from any object with dim/n/h/origin/nodes/
+    normals/weights attributes (the shared input generators make those)."""
+    d = geom.dim
+    return Problem(kernel, float(geom.h), np.asarray(geom.origin[:d], dtype=np.float64),
+                   np.asarray(geom.n[:d], dtype=np.int64),
+                   np.ascontiguousarray(geom.nodes, dtype=np.float64),
+                   np.ascontiguousarray(geom.normals, dtype=np.float64),
+                   np.ascontiguousarray(geom.weights, dtype=np.float64), nu, mu)
+
+
+def snap(p: Problem) -> np.ndarray:
+    """Grid index of every node: floor((x - origin)/h + 1/2)."""
+    g = np.zeros((p.m, p.dim), dtype=np.int64)
+    bad = lib().orc_snap(p.dim, p.m, _d(p.nodes), p.h, _d(p.origin), _l(p.n.astype(np.int64)), _l(g))
+    if bad >= 0:
+        raise ValueError(f"node {bad} lies outside the grid")
+    return g
+
+
+def apply(p: Problem, q, u, cmode=C_IMPLICIT, cuser=None, targets=None, with_scale=False,
+          with_c=False):
+    """r = c u + D[u] - S[q] at the targets (a contiguous range ``(t0, t1)`` or
+    None for all nodes).  ``q``/``u``: (ncomp, m) or (m,) for Laplace."""
+    g = snap(p)
+    nc = p.ncomp
+    q = np.ascontiguousarray(np.reshape(q, (nc, p.m)), dtype=np.float64)
+    u = np.ascontiguousarray(np.reshape(u, (nc, p.m)), dtype=np.float64)
+    t0, t1 = (0, p.m) if targets is None else targets
+    nt = t1 - t0
+    r = np.zeros((nc, nt))
+    sc = np.zeros((nc, nt))
+    cbuf = np.zeros((nt, nc * nc))
+    if cmode == C_USER:
+        cu = np.ascontiguousarray(np.reshape(cuser, (p.m, nc * nc)), dtype=np.float64)
+        cptr = _d(cu)
+    else:
+        cu = None
+        cptr = None
+    lib().orc_apply(p.kernel, p.nu, p.mu, p.h, p.m, _l(g), _d(p.normals), _d(p.weights), cmode,
+                    cptr, _d(q), _d(u), t0, t1, _d(r), _d(sc), _d(cbuf))
+    out = [r if nc > 1 else r[0]]
+    if with_scale:
+        out.append(sc if nc > 1 else sc[0])
+    if with_c:
+        out.append(cbuf.reshape(nt, nc, nc) if nc > 1 else cbuf[:, 0])
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def assemble(p: Problem):
+    """Dense S, D ((nc m) x (nc m), component-major) and the implicit c blocks."""
+    g = snap(p)
+    n = p.ncomp * p.m
+    S = np.zeros((n, n))
+    D = np.zeros((n, n))
+    c = np.zeros((p.m, p.ncomp * p.ncomp))
+    lib().orc_assemble(p.kernel, p.nu, p.mu, p.h, p.m, _l(g), _d(p.normals), _d(p.weights),
+                       _d(S), _d(D), _d(c))
+    return S, D, c
+
+
+def c_matrix(p: Problem, cmode, cuser=None, c_implicit=None):
+    """The free-term operator as a dense (nc m)^2 matrix (component-major)."""
+    nc, m = p.ncomp, p.m
+    if cmode == C_HALF:
+        blocks = np.tile(0.5 * np.eye(nc).reshape(1, nc * nc), (m, 1))
+    elif cmode == C_USER:
+        blocks = np.reshape(cuser, (m, nc * nc))
+    else:
+        blocks = c_implicit
+    C = np.zeros((nc * m, nc * m))
+    idx = np.arange(m)
+    for a in range(nc):
+        for b in range(nc):
+            C[a * m + idx, b * m + idx] = blocks[:, a * nc + b]
+    return C
+
+
+def mixed_system(p: Problem, bc, known, cmode=C_IMPLICIT, cuser=None):
+    """Dense A, b of the mixed boundary-value problem: unknown x holds q where
+    u is given (bc == 0) and u where q is given (bc == 1); A x = b is
+    "r = 0" (eq. 4 / 8) with the known values moved to the right."""
+    S, D, cimp = assemble(p)
+    C = c_matrix(p, cmode, cuser, cimp)
+    bc = np.reshape(bc, -1).astype(bool)          # True: q known
+    known = np.reshape(known, -1)
+    # r = (C + D) u - S q ;  columns of unknowns
+    Au = C + D
+    As = -S
+    A = np.where(bc[None, :], Au, As)
+    Bk = np.where(bc[None, :], As, Au)
+    b = -Bk @ known
+    return A, b
+
+
+def solve_lu(p: Problem, bc, known, cmode=C_IMPLICIT, cuser=None):
+    """Textbook dense LU solve of the mixed system (small problems)."""
+    A, b = mixed_system(p, bc, known, cmode, cuser)
+    x = np.linalg.solve(A, b)
+    return x.reshape(p.ncomp, p.m) if p.ncomp > 1 else x
