@@ -1,0 +1,182 @@
+"""Benchmark of the grid-embedded FFT BEM operator on one MI355X.
+
+Workload: 3D Laplace, FP32 transforms, unit-cube surface with 100 grid points
+per edge (58,808 nodes) voxelised on a 128^3 grid, FFT padded to 256^3.  One
+step = one apply r = c u + D[u] - S[q] (all four kernels) on device-resident
+inputs; value = applies per second.  Also reported: per-stage HIP-event
+times and the roofline of the dominant stage, the sphere (R = 0.35) and FP64
+variants, GMRES time-to-solve at relative true residual 1e-6 for the mixed
+problem (Dirichlet above the centre, Neumann below), and the CPU oracle on a
+bounded sample of targets.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BEM matvecs/s + GMRES time-to-solve @1e-6 rel. residual; HBM roofline fraction"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(info, prec_bytes):
+    """Algorithmic HBM bytes of each stage for one apply (the bytes each
+    kernel must read or write once; node data O(M) included)."""
+    px, py, pz = info["pad"]
+    hx, hy, hz = px // 2 + 1, py // 2 + 1, pz // 2 + 1
+    nzo = info["z_count"]
+    F, K, O, m = info["nfields"], info["nspectra"], info["noutputs"], info["m"]
+    cb = 2 * prec_bytes
+    g = hx * nzo * py * cb                     # one complex field after the y transform
+    spec = K * hx * hy * hz * prec_bytes       # octant spectra
+    nodes_in = m * (8 * 2 * info["ncomp"] + 4 * 4 + 8 * 4)
+    return {
+        "fwd_xy": F * g + nodes_in,
+        "zpass": F * g + spec + O * g,
+        "inv_yx": O * g + m * 8 * O * 2,
+        "epilogue": m * 8 * O * (2 + 2 * O),
+    }
+
+
+def timed_applies(plan, q, u, r, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        plan.apply(q, u, r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(q, u, r)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(geom, q, u, budget_s=12.0):
+    import oracle as O
+
+    p = O.problem(geom, O.LAPLACE3D)
+    t = time.perf_counter()
+    O.apply(p, q, u, targets=(0, 200))
+    per = (time.perf_counter() - t) / 200.0
+    nt = int(max(200, min(geom.m, budget_s / max(per, 1e-9))))
+    t = time.perf_counter()
+    O.apply(p, q, u, targets=(0, nt))
+    dt = time.perf_counter() - t
+    full = dt / nt * geom.m
+    return {"value": 1.0 / full, "unit": "matvec/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"direct-sum FP64 oracle on targets 0..{nt} of {geom.m} (all sources), "
+                      f"{dt:.1f} s, scaled to one full apply ({full:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="apply timing only (for profilers)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the operator is not sharded",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1809_00845_amd import binding as B
+    from paper_1809_00845_amd import inputs as I
+
+    B.load()  # raises if the HIP library is missing
+    dev = torch.device("cuda:0")
+    cube = I.cube3d(128, 100)
+    uh, qh = I.harmonic_3d_xyz(cube)
+    noise = I.uniform_noise(cube.m, 0, 2)
+    qn, un = qh + noise[0], uh + noise[1]
+    q = torch.tensor(qn, device=dev)
+    u = torch.tensor(un, device=dev)
+    r = torch.empty_like(u)
+
+    plan = B.Plan(cube, B.LAPLACE3D, precision=B.FP32)
+    info = plan.info()
+    dt = timed_applies(plan, q, u, r, args.steps, args.warmup)
+    value = args.steps / dt
+    stage_ms = B.bemfft_apply_profile(plan.handle, q, u, r, reps=max(20, args.steps // 4))
+    sb = stage_bytes(info, 4)
+    names = ["fwd_xy", "zpass", "inv_yx", "epilogue"]
+    stages = {n: {"ms": ms, "gbs": sb[n] / (ms * 1e-3) / 1e9, "bytes": sb[n]} for n, ms in zip(names, stage_ms)}
+    dom = max(names, key=lambda n: stages[n]["ms"])
+    apply_bytes = sum(sb.values())
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "laplace3d_cube_surface_128cubed_pad256_fp32", "nodes": cube.m, "grid": 128,
+                   "pad": 256, "edge_points": 100, "occupied_planes": info["z_count"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": stages[dom]["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": stages[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None},
+        "stages": stages,
+        "apply_gbs": apply_bytes / (sum(stage_ms) * 1e-3) / 1e9,
+    }
+    if not args.quick:
+        extra = {}
+        # FP64 apply, same cube
+        plan64 = B.Plan(cube, B.LAPLACE3D, precision=B.FP64)
+        dt64 = timed_applies(plan64, q, u, r, max(20, args.steps // 4), 5)
+        extra["cube_fp64_matvec_s"] = max(20, args.steps // 4) / dt64
+        # sphere
+        sph = I.sphere3d(128, 0.35)
+        us, qs = I.harmonic_3d_xyz(sph)
+        ns = I.uniform_noise(sph.m, 0, 2)
+        qsd = torch.tensor(qs + ns[0], device=dev)
+        usd = torch.tensor(us + ns[1], device=dev)
+        rs = torch.empty_like(usd)
+        psph = B.Plan(sph, B.LAPLACE3D, precision=B.FP32)
+        dts = timed_applies(psph, qsd, usd, rs, args.steps, 5)
+        extra["sphere_nodes"] = sph.m
+        extra["sphere_fp32_matvec_s"] = args.steps / dts
+        # time to solve, mixed BC, 1e-6 true relative residual
+        solves = {}
+        for name, g, pl32, pl64 in (("cube", cube, plan, plan64), ("sphere", sph, psph, None)):
+            uu, qq = I.harmonic_3d_xyz(g)
+            bc = I.mixed_bc_upper(g)
+            known = torch.tensor(np.where(bc == 0, uu, qq), device=dev)
+            bct = torch.tensor(bc, device=dev)
+            if pl64 is None:
+                pl64 = B.Plan(g, B.LAPLACE3D, precision=B.FP64)
+            for tag, pl in (("fp64", pl64), ("fp32", pl32)):
+                pl.solve(bct, known, tol=1e-6)  # warm (workspace allocation)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, si = pl.solve(bct, known, tol=1e-6)
+                torch.cuda.synchronize()
+                solves[f"{name}_{tag}"] = {"seconds": time.perf_counter() - t0, "iters": si["iters"],
+                                           "true_relres": si["true_relres"], "status": si["status"]}
+        extra["time_to_solve_1e-6"] = solves
+        extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
+        out["extra"] = extra
+        if not args.no_cpu:
+            out["cpu_baseline"] = cpu_baseline(cube, qn, un)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

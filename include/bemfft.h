@@ -1,0 +1,205 @@
+/*
+ * bemfft.h -- C ABI of the grid-embedded FFT boundary-element operator for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (Benad, "Acceleration of the Boundary Element Method for arbitrary
+ * shapes with the Fast Fourier Transformation"):
+ *   The boundary integral equation of Laplace's equation (eq. 4) and of
+ *   Navier's equation (eq. 8),
+ *       c u(x0) = int q u*(x - x0) dS - int u q*(x - x0) dS,
+ *   is not a convolution over the boundary, but it is one over the space one
+ *   dimension higher that encloses it (Sec. 3).  The boundary data are put on
+ *   a uniform grid, zero wherever there is no boundary (Fig. 4), the kernels
+ *   are sampled on the padded grid (Fig. 5), and each integral becomes
+ *   IFFT(FFT(field) * FFT(kernel)) (eq. 16), read back at the boundary nodes.
+ *   The unknown half of the boundary data is found by an iterative solve in
+ *   which this convolution is the matrix-vector product (end of Sec. 4).
+ *
+ * Discrete operator (one row per boundary node j, p_j its grid point):
+ *     r_j = c_j u_j + D[u]_j - S[q]_j
+ *     S[q]_j = sum_k G(p_k - p_j) w_k q_k,   D[u]_j = sum_k H(p_k - p_j; n_k) w_k u_k
+ *   G: single-layer kernel (u* of eq. 3 in 2D, 1/(4 pi r) in 3D, Kelvin's
+ *   tensor of eq. 7); H: double-layer kernel (q* of eq. 12 / its 3D analogue,
+ *   Kelvin's traction kernel).  w_k: boundary measure of node k (the "divide
+ *   by the discretisation length" of Sec. 4 folded into a weight).  Pairs in
+ *   one grid cell: single layer uses the grid value at offset 0 (flat-panel
+ *   integral over h^(d-1), divided by it; Navier: orientation average), the
+ *   node itself uses the flat-panel integral over its own w_j; double layer 0.
+ *
+ * Conventions for every call:
+ *   - All functions return an int status: 0 = success, < 0 = error (the
+ *     object is left unchanged), > 0 = a non-fatal condition (see below).
+ *     bemfft_last_error() gives a thread-local message for the last failure.
+ *   - Device vectors are component-major ("SoA"): [ncomp][m] doubles, with
+ *     ncomp = 1 for Laplace and 3 for Navier, in the caller's node order.
+ *   - Host arrays are copied before the call returns; the library never
+ *     keeps a caller pointer.
+ *   - A plan is used by one stream at a time (it owns one workspace); create
+ *     one plan per concurrent stream.
+ *   - stream: a hipStream_t (NULL = the legacy default stream).
+ */
+#ifndef BEMFFT_H
+#define BEMFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- statuses */
+#define BEMFFT_OK 0
+#define BEMFFT_EINVAL (-1)     /* bad argument: sizes, nodes off the grid, ...   */
+#define BEMFFT_ENOMEM (-2)     /* device or host allocation failed               */
+#define BEMFFT_EDEVICE (-3)    /* a HIP runtime call failed                      */
+#define BEMFFT_EUNSUPPORTED (-4) /* a padded size with no compiled FFT plan      */
+#define BEMFFT_EBREAKDOWN (-5) /* non-finite values in a solve                   */
+#define BEMFFT_ENOCONV 1       /* solve stopped at maxit; result still written   */
+
+typedef struct bemfft_plan bemfft_plan; /* opaque; owns all device state */
+
+/* Kernel families: eq. (3) Laplace 2D, its 3D analogue, eq. (7) Kelvin. */
+typedef enum { BEMFFT_LAPLACE2D = 0, BEMFFT_LAPLACE3D = 1, BEMFFT_NAVIER3D = 2 } bemfft_kernel;
+
+/* Arithmetic of the transforms and the spectral product.  Kernel spectra are
+ * always computed in FP64 and rounded to the working precision. */
+typedef enum { BEMFFT_FP64 = 0, BEMFFT_FP32 = 1 } bemfft_precision;
+
+/* Free term c of eq. (4)/(8): 1/2 (smooth boundary), user values, or the
+ * implicit c_j = -D[1]_j (Navier: C_j = -[D e_1, D e_2, D e_3]_j). */
+typedef enum { BEMFFT_C_HALF = 0, BEMFFT_C_USER = 1, BEMFFT_C_IMPLICIT = 2 } bemfft_cmode;
+
+/* Uniform grid: n[a] points per axis at origin + h * g, g in [0, n[a]).
+ * dim = 2 uses n[0], n[1] (n[2] ignored).  pad[a] = padded FFT length per
+ * axis; 0 picks the smallest supported even length >= 2 n[a] ("extended in
+ * the appropriate fashion", Sec. 4). */
+typedef struct {
+    int dim;
+    int64_t n[3];
+    double h;
+    double origin[3];
+    int64_t pad[3];
+} bemfft_grid;
+
+typedef struct {
+    bemfft_precision precision; /* default BEMFFT_FP64                        */
+    bemfft_cmode c_mode;        /* default BEMFFT_C_IMPLICIT                  */
+    const double *c_user;       /* host; m values (Laplace) or m*9 row-major
+                                   3x3 blocks (Navier); read if C_USER         */
+    void *stream;               /* stream used by plan_create's device work   */
+} bemfft_plan_opts;
+
+/*
+ * Create a plan for one boundary (eq. 4 / eq. 8 on the grid of Sec. 3).
+ *   out      receives the plan (set to NULL on failure).
+ *   grid     see bemfft_grid.
+ *   m        number of boundary nodes (>= 1).
+ *   nodes    host, m*dim doubles, row-major positions; each is snapped to the
+ *            grid point floor((x - origin)/h + 1/2), which must lie in [0, n).
+ *   normals  host, m*dim: mean outward normal of the node's boundary piece.
+ *   weights  host, m: arc length (2D) / area (3D) of the piece, > 0; NULL
+ *            means h^(dim-1) for every node (the paper's grid-aligned case).
+ *   kernel   bemfft_kernel (must match grid->dim).
+ *   nu, mu   Poisson ratio in (-1, 1/2) and shear modulus > 0 (Navier only).
+ *   opts     NULL for defaults.
+ * The plan samples the kernels on the padded grid, transforms them in FP64,
+ * keeps one octant of each real (or imaginary) spectrum, and for C_IMPLICIT
+ * runs the FP64 operator once per rigid mode.  Errors: EINVAL, ENOMEM,
+ * EDEVICE, EUNSUPPORTED.
+ */
+int bemfft_plan_create(bemfft_plan **out, const bemfft_grid *grid, int64_t m,
+                       const double *nodes, const double *normals, const double *weights,
+                       int kernel, double nu, double mu, const bemfft_plan_opts *opts);
+
+/*
+ * r = c u + D[u] - S[q] (the residual of eq. 4 / eq. 8 at every node),
+ * evaluated as the zero-padded FFT convolution of eq. (16).
+ *   q, u   device, [ncomp][m] doubles (q is the flux, Navier: traction t).
+ *   r      device, [ncomp][m] doubles, written; may not alias q or u.
+ *   stream hipStream_t; asynchronous, no host synchronisation.
+ * Errors: EINVAL (NULL pointers), EDEVICE.
+ */
+int bemfft_apply(bemfft_plan *p, const double *q, const double *u, double *r, void *stream);
+
+/*
+ * Same as bemfft_apply, repeated 'reps' times with HIP events recorded on
+ * 'stream' between the four stages (scatter + x/y transforms, z transform +
+ * spectral products, inverse y transform + gather, epilogue); stage_ms[4]
+ * receives the mean duration of each stage in milliseconds.  Synchronises
+ * the stream.  For measurement only.  Errors: EINVAL, EDEVICE.
+ */
+int bemfft_apply_profile(bemfft_plan *p, const double *q, const double *u, double *r, int reps,
+                         double *stage_ms, void *stream);
+
+/* Options of the iterative solve (GMRES, restarted, right Jacobi). */
+typedef struct {
+    double tol;     /* stop when ||b - A x||_2 <= tol ||b||_2 (default 1e-6) */
+    int restart;    /* Krylov basis size (default 100, max 400)               */
+    int maxit;      /* total iterations (default 1000)                        */
+    int precond;    /* 0 none, 1 Jacobi (default 1)                           */
+    int use_x0;     /* 1: 'unknown' holds the initial guess on entry          */
+} bemfft_solve_opts;
+
+typedef struct {
+    int iters;          /* GMRES iterations (operator applications)           */
+    int restarts;
+    double true_relres; /* ||b - A x|| / ||b|| recomputed with a fresh apply  */
+    int status;         /* same as the return value                          */
+    double seconds;     /* wall time of the call                              */
+} bemfft_solve_info;
+
+/*
+ * Solve the mixed boundary-value problem (Sec. 4: u given, q sought; the
+ * general case mixes both per node):
+ *   bc       device, [ncomp][m] uint8: 0 = u known (Dirichlet), 1 = q known.
+ *   known    device, [ncomp][m]: the given value per slot.
+ *   unknown  device, [ncomp][m]: the other value per slot (q where bc = 0,
+ *            u where bc = 1); on entry the initial guess if use_x0.
+ * Unknowns x satisfy A x = b with A x = apply(x in the unknown slots) and
+ * b = -apply(known values).  Arnoldi, Givens rotations and the true residual
+ * are FP64.  Returns 0, ENOCONV (maxit reached; x and info still written),
+ * EBREAKDOWN (non-finite values), EINVAL, EDEVICE.  Synchronises 'stream'
+ * once per iteration (the convergence scalar crosses to the host).
+ */
+int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
+                 const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
+
+/* Facts about a plan (host copies). */
+typedef struct {
+    int dim, kernel, precision, c_mode;
+    int64_t m, ncomp;
+    int64_t n[3], pad[3];
+    int64_t z_lo, z_count;       /* occupied grid planes along the last axis   */
+    int64_t nfields, nspectra, noutputs;
+    int64_t workspace_bytes, spectra_bytes;
+    double spectrum_parity_residual; /* max discarded (imag or real) part of
+                                        the kernel spectra / max |spectrum|     */
+    double plan_seconds;
+} bemfft_plan_info;
+
+int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info);
+
+/* Copy the free-term values c_j in use (host; m or m*9 doubles). */
+int bemfft_plan_get_c(const bemfft_plan *p, double *c_host);
+
+/* Release all device state of the plan.  NULL is accepted. */
+int bemfft_plan_destroy(bemfft_plan *p);
+
+/* In-place FP64 complex 3D FFT of a device array [pz][py][px] of interleaved
+ * (re, im) doubles with the library's own transform kernels (the transform
+ * used for the kernel spectra); direction -1 forward, +1 inverse (unscaled).
+ * Lengths must be supported FFT sizes or 1.  Provided for testing. */
+int bemfft_fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int direction,
+                         void *stream);
+
+/* Human-readable name of a status; thread-local detail of the last error. */
+const char *bemfft_strerror(int status);
+const char *bemfft_last_error(void);
+
+/* Supported padded FFT lengths (fills up to cap entries; returns the count). */
+int bemfft_supported_sizes(int64_t *sizes, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEMFFT_H */

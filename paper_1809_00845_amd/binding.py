@@ -1,0 +1,261 @@
+"""ctypes binding of libbemfft.so -- argument marshalling only.
+
+Every step of the operator and the solve runs in the HIP library; this
+module converts numpy/torch arguments to pointers and status codes to
+exceptions.  It raises if the library is missing: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbemfft.so")
+
+LAPLACE2D, LAPLACE3D, NAVIER3D = 0, 1, 2
+FP64, FP32 = 0, 1
+C_HALF, C_USER, C_IMPLICIT = 0, 1, 2
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBREAKDOWN, ENOCONV = 0, -1, -2, -3, -4, -5, 1
+
+
+class bemfft_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("origin", ctypes.c_double * 3), ("pad", ctypes.c_int64 * 3)]
+
+
+class bemfft_plan_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("c_mode", ctypes.c_int),
+                ("c_user", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
+
+
+class bemfft_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("precond", ctypes.c_int), ("use_x0", ctypes.c_int)]
+
+
+class bemfft_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("true_relres", ctypes.c_double),
+                ("status", ctypes.c_int), ("seconds", ctypes.c_double)]
+
+
+class bemfft_plan_info(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("kernel", ctypes.c_int), ("precision", ctypes.c_int),
+                ("c_mode", ctypes.c_int), ("m", ctypes.c_int64), ("ncomp", ctypes.c_int64),
+                ("n", ctypes.c_int64 * 3), ("pad", ctypes.c_int64 * 3), ("z_lo", ctypes.c_int64),
+                ("z_count", ctypes.c_int64), ("nfields", ctypes.c_int64), ("nspectra", ctypes.c_int64),
+                ("noutputs", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("spectra_bytes", ctypes.c_int64), ("spectrum_parity_residual", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double)]
+
+
+EXPORTS = [
+    "bemfft_plan_create", "bemfft_apply", "bemfft_apply_profile", "bemfft_solve", "bemfft_plan_get_info", "bemfft_plan_get_c",
+    "bemfft_plan_destroy", "bemfft_fft3d_c2c_f64", "bemfft_strerror", "bemfft_last_error",
+    "bemfft_supported_sizes",
+]
+
+_lib = None
+
+
+class BemfftError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status}): {last_error()}")
+
+
+def load():
+    """Load the HIP library (built by paper_1809_00845_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_1809_00845_amd.build.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    L.bemfft_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(bemfft_grid), i64, dp, dp, dp,
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(bemfft_plan_opts)]
+    L.bemfft_apply.argtypes = [vp, vp, vp, vp, vp]
+    L.bemfft_apply_profile.argtypes = [vp, vp, vp, vp, ctypes.c_int, dp, vp]
+    L.bemfft_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(bemfft_solve_opts),
+                               ctypes.POINTER(bemfft_solve_info), vp]
+    L.bemfft_plan_get_info.argtypes = [vp, ctypes.POINTER(bemfft_plan_info)]
+    L.bemfft_plan_get_c.argtypes = [vp, dp]
+    L.bemfft_plan_destroy.argtypes = [vp]
+    L.bemfft_fft3d_c2c_f64.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp]
+    L.bemfft_strerror.argtypes = [ctypes.c_int]
+    L.bemfft_strerror.restype = ctypes.c_char_p
+    L.bemfft_last_error.restype = ctypes.c_char_p
+    L.bemfft_supported_sizes.argtypes = [ctypes.POINTER(i64), ctypes.c_int]
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return load().bemfft_strerror(status).decode()
+
+
+def last_error() -> str:
+    return load().bemfft_last_error().decode()
+
+
+def _check(status, where):
+    if status < 0:
+        raise BemfftError(status, where)
+    return status
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (must be contiguous)."""
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def supported_sizes():
+    buf = (ctypes.c_int64 * 32)()
+    n = load().bemfft_supported_sizes(buf, 32)
+    return [int(buf[i]) for i in range(n)]
+
+
+def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.0, origin=(0.0, 0.0, 0.0),
+                       pad=(0, 0, 0), precision=FP64, c_mode=C_IMPLICIT, c_user=None, stream=None):
+    """Returns an opaque plan handle (ctypes.c_void_p)."""
+    L = load()
+    g = bemfft_grid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = int(n[a]) if a < len(n) else 1
+        g.origin[a] = float(origin[a]) if a < len(origin) else 0.0
+        g.pad[a] = int(pad[a]) if a < len(pad) else 0
+    g.h = float(h)
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    normals = np.ascontiguousarray(normals, dtype=np.float64)
+    m = nodes.shape[0]
+    wptr = None
+    if weights is not None:
+        weights = np.ascontiguousarray(weights, dtype=np.float64)
+        wptr = weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    opts = bemfft_plan_opts()
+    opts.precision = precision
+    opts.c_mode = c_mode
+    if c_user is not None:
+        c_user = np.ascontiguousarray(c_user, dtype=np.float64)
+        opts.c_user = c_user.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    opts.stream = _stream_ptr(stream) if stream is not None else None
+    h_ = ctypes.c_void_p()
+    st = L.bemfft_plan_create(ctypes.byref(h_), ctypes.byref(g), m,
+                              nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              normals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wptr, kernel,
+                              float(nu), float(mu), ctypes.byref(opts))
+    _check(st, "bemfft_plan_create")
+    return h_
+
+
+def bemfft_apply(plan, q, u, r, stream=None):
+    return _check(load().bemfft_apply(plan, _ptr(q), _ptr(u), _ptr(r), _stream_ptr(stream)), "bemfft_apply")
+
+
+def bemfft_apply_profile(plan, q, u, r, reps=10, stream=None):
+    """Mean per-stage milliseconds (fwd_xy, zpass, inv_yx, epilogue)."""
+    ms = (ctypes.c_double * 4)()
+    _check(load().bemfft_apply_profile(plan, _ptr(q), _ptr(u), _ptr(r), int(reps), ms, _stream_ptr(stream)),
+           "bemfft_apply_profile")
+    return [float(v) for v in ms]
+
+
+def bemfft_solve(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, precond=1, use_x0=0,
+                 stream=None):
+    o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0)
+    info = bemfft_solve_info()
+    st = load().bemfft_solve(plan, _ptr(bc), _ptr(known), _ptr(unknown), ctypes.byref(o), ctypes.byref(info),
+                             _stream_ptr(stream))
+    _check(st, "bemfft_solve")
+    return {"status": st, "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
+            "seconds": info.seconds}
+
+
+def bemfft_plan_get_info(plan):
+    info = bemfft_plan_info()
+    _check(load().bemfft_plan_get_info(plan, ctypes.byref(info)), "bemfft_plan_get_info")
+    out = {}
+    for name, _ in bemfft_plan_info._fields_:
+        v = getattr(info, name)
+        out[name] = list(v) if not isinstance(v, (int, float)) else v
+    return out
+
+
+def bemfft_plan_get_c(plan, m, ncomp):
+    buf = np.zeros(m * ncomp * ncomp)
+    _check(load().bemfft_plan_get_c(plan, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "bemfft_plan_get_c")
+    return buf if ncomp == 1 else buf.reshape(m, ncomp, ncomp)
+
+
+def bemfft_plan_destroy(plan):
+    if plan is not None and plan.value:
+        load().bemfft_plan_destroy(plan)
+
+
+def bemfft_fft3d_c2c_f64(data, px, py, pz, direction, stream=None):
+    return _check(load().bemfft_fft3d_c2c_f64(_ptr(data), px, py, pz, direction, _stream_ptr(stream)),
+                  "bemfft_fft3d_c2c_f64")
+
+
+class Plan:
+    """Owns one plan; geometry from any object with dim/n/h/origin/nodes/
+    normals/weights attributes."""
+
+    def __init__(self, geom, kernel, precision=FP64, c_mode=C_IMPLICIT, c_user=None, nu=0.3, mu=1.0,
+                 pad=(0, 0, 0), stream=None):
+        self.kernel = kernel
+        self.ncomp = 3 if kernel == NAVIER3D else 1
+        self.m = int(np.asarray(geom.weights).shape[0])
+        self.handle = bemfft_plan_create(geom.dim, geom.n, geom.h, geom.nodes, geom.normals, geom.weights,
+                                         kernel, nu, mu, origin=geom.origin, pad=pad, precision=precision,
+                                         c_mode=c_mode, c_user=c_user, stream=stream)
+
+    def apply(self, q, u, r=None, stream=None):
+        import torch
+
+        if r is None:
+            r = torch.empty_like(u)
+        bemfft_apply(self.handle, q, u, r, stream)
+        return r
+
+    def solve(self, bc, known, unknown=None, **kw):
+        import torch
+
+        if unknown is None:
+            unknown = torch.zeros_like(known)
+            kw.setdefault("use_x0", 0)
+        info = bemfft_solve(self.handle, bc, known, unknown, **kw)
+        return unknown, info
+
+    def info(self):
+        return bemfft_plan_get_info(self.handle)
+
+    def c(self):
+        return bemfft_plan_get_c(self.handle, self.m, self.ncomp)
+
+    def close(self):
+        bemfft_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None:
+                self.close()
+        except Exception:
+            pass

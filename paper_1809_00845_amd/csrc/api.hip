@@ -1,0 +1,570 @@
+// api.hip -- plan creation, the apply entry point and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "apply_impl.hpp"
+#include "fft_device.hpp"
+#include "internal.hpp"
+#include "kinds.hpp"
+
+namespace bemfft {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr double kPi = 3.141592653589793238462643383279502884;
+const int64_t kSizes[] = {32, 64, 96, 128, 192, 256, 320, 384, 512};
+
+template <typename T>
+int dev_upload(T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    if (src.empty()) return 0;
+    if (hipMalloc(dst, src.size() * sizeof(T)) != hipSuccess) {
+        set_error("hipMalloc failed");
+        return BEMFFT_ENOMEM;
+    }
+    BF_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return 0;
+}
+
+void dev_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+// Flat-panel self integrals of the single-layer kernel over a node's own
+// measure w (straight segment in 2D, square in 3D), and the grid value at
+// offset 0 (the same integral for the reference measure h^(d-1), per unit
+// measure; Navier: orientation averaged).  O x O blocks, row-major.
+void self_blocks(int kernel, double w, const double n[3], double h, double nu, double mu, double *self,
+                 double *k0w) {
+    const double l = std::log(1.0 + std::sqrt(2.0));
+    if (kernel == BEMFFT_LAPLACE2D) {
+        self[0] = w * (1.0 - std::log(0.5 * w)) / (2.0 * kPi);
+        k0w[0] = w * (1.0 - std::log(0.5 * h)) / (2.0 * kPi);
+        return;
+    }
+    if (kernel == BEMFFT_LAPLACE3D) {
+        self[0] = std::sqrt(w) * l / kPi;
+        k0w[0] = w * l / (kPi * h);
+        return;
+    }
+    const double pre = 1.0 / (16.0 * kPi * mu * (1.0 - nu));
+    const double i1 = 4.0 * std::sqrt(w) * l;
+    const double i1ref = 4.0 * l / h;  // per unit measure
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) {
+            const double d = (k == j) ? 1.0 : 0.0;
+            self[3 * k + j] = pre * i1 * ((3.0 - 4.0 * nu) * d + 0.5 * (d - n[k] * n[j]));
+            k0w[3 * k + j] = pre * i1ref * w * ((3.0 - 4.0 * nu) + 1.0 / 3.0) * d;
+        }
+}
+
+template <typename R>
+std::vector<cx<R>> twiddle_table(int64_t p) {
+    std::vector<cx<R>> t(p);
+    for (int64_t i = 0; i < p; ++i) {
+        ctrig::CS w = ctrig::cs2pi(i, p);
+        t[i] = {(R)w.c, (R)(-w.s)};
+    }
+    return t;
+}
+
+int64_t auto_pad(int64_t n) {
+    for (int64_t s : kSizes)
+        if (s >= 2 * n) return s;
+    return -1;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+void free_engine(Engine *e) {
+    dev_free(e->spec);
+    dev_free(e->twx);
+    dev_free(e->twy);
+    dev_free(e->twz);
+    dev_free(e->Y);
+    dev_free(e->Z);
+    dev_free(e->partial);
+    dev_free(e->vf);
+    *e = Engine{};
+}
+
+template <typename R>
+static int upload_tw(Engine *e, const bemfft_plan *p) {
+    cx<R> *d = nullptr;
+    BF_CHECK(dev_upload(&d, twiddle_table<R>(p->P[0])));
+    e->twx = d;
+    BF_CHECK(dev_upload(&d, twiddle_table<R>(p->P[1])));
+    e->twy = d;
+    BF_CHECK(dev_upload(&d, twiddle_table<R>(p->P[2])));
+    e->twz = d;
+    return 0;
+}
+
+int upload_twiddles(Engine *e, const bemfft_plan *p) {
+    return e->precision == BEMFFT_FP32 ? upload_tw<float>(e, p) : upload_tw<double>(e, p);
+}
+
+static int inv_kxc(int kernel, int precision, int py) {
+    if (kernel == 0) return inv_kxc_kind<0>(precision, py);
+    if (kernel == 1) return inv_kxc_kind<1>(precision, py);
+    return inv_kxc_kind<2>(precision, py);
+}
+
+int alloc_workspace(bemfft_plan *p, Engine *e) {
+    const size_t cb = 2 * e->creal;
+    const size_t rows = (size_t)p->H[0] * p->nzo * p->P[1];
+    const int kxc = inv_kxc(p->kernel, e->precision, (int)p->P[1]);
+    if (kxc <= 0) {
+        set_error("unsupported y length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    e->G = (int)((p->H[0] + kxc - 1) / kxc);
+    const size_t spec = (size_t)p->K * p->H[0] * p->H[1] * p->H[2] * e->creal;
+    const size_t ysz = (size_t)p->F * rows * cb, zsz = (size_t)p->O * rows * cb;
+    const size_t psz = (size_t)e->G * p->O * p->m * sizeof(double);
+    const size_t vsz = (size_t)p->F * p->m * e->creal;
+    if (hipMalloc(&e->spec, spec) != hipSuccess || hipMalloc(&e->Y, ysz) != hipSuccess ||
+        hipMalloc(&e->Z, zsz) != hipSuccess || hipMalloc(&e->partial, psz) != hipSuccess ||
+        hipMalloc(&e->vf, vsz) != hipSuccess) {
+        set_error("hipMalloc of the workspace failed");
+        return BEMFFT_ENOMEM;
+    }
+    e->bytes = spec + ysz + zsz + psz + vsz;
+    return 0;
+}
+
+int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double *u, double *r, hipStream_t st,
+                 hipEvent_t *ev) {
+    ApplyArgs a{};
+    a.nx = (int)p->n[0];
+    a.ny = (int)p->n[1];
+    a.nz = (int)p->n[2];
+    a.px = (int)p->P[0];
+    a.py = (int)p->P[1];
+    a.pz = (int)p->P[2];
+    a.hx = (int)p->H[0];
+    a.hy = (int)p->H[1];
+    a.hz = (int)p->H[2];
+    a.z0 = (int)p->z0;
+    a.nzo = (int)p->nzo;
+    a.m = (int)p->m;
+    a.G = e.G;
+    a.gx = p->d_gx;
+    a.gy = p->d_gy;
+    a.rowptr = p->d_rowptr;
+    a.perm = p->d_perm;
+    a.w = p->d_w;
+    a.nrm = p->d_nrm;
+    a.C = p->d_C;
+    a.SC = p->d_SC;
+    a.q = q;
+    a.u = u;
+    a.r = r;
+    a.spec = e.spec;
+    a.twx = e.twx;
+    a.twy = e.twy;
+    a.twz = e.twz;
+    a.Y = e.Y;
+    a.Z = e.Z;
+    a.partial = e.partial;
+    a.vf = e.vf;
+    a.node_splits = (int)std::max<int64_t>(1, (p->max_plane_nodes + kGatherChunk - 1) / kGatherChunk);
+    if (p->kernel == 0) return apply_kind<0>(e.precision, a, st, ev);
+    if (p->kernel == 1) return apply_kind<1>(e.precision, a, st, ev);
+    return apply_kind<2>(e.precision, a, st, ev);
+}
+
+}  // namespace bemfft
+
+using namespace bemfft;
+
+namespace {
+
+void destroy_plan_state(bemfft_plan *p) {
+    free_engine(&p->eng);
+    dev_free(p->d_gx);
+    dev_free(p->d_gy);
+    dev_free(p->d_gz);
+    dev_free(p->d_perm);
+    dev_free(p->d_rowptr);
+    dev_free(p->d_w);
+    dev_free(p->d_nrm);
+    dev_free(p->d_C);
+    dev_free(p->d_SC);
+    dev_free(p->s_V);
+    dev_free(p->s_vec);
+    dev_free(p->s_red);
+    dev_free(p->s_hbuf);
+    if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+}
+
+// Implicit free term: c_j = -D[1]_j (Laplace), C_j = -[D e_1, D e_2, D e_3]_j
+// (Navier), from the FP64 operator with c = 0 and q = 0.
+int implicit_free_term(bemfft_plan *p, const Engine &e64, hipStream_t st, std::vector<double> &Cs) {
+    const int64_t m = p->m;
+    const int nc = p->ncomp;
+    double *q = nullptr, *u = nullptr, *r = nullptr;
+    const size_t bytes = (size_t)nc * m * sizeof(double);
+    if (hipMalloc(&q, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess || hipMalloc(&r, bytes) != hipSuccess) {
+        dev_free(q);
+        dev_free(u);
+        dev_free(r);
+        set_error("hipMalloc failed");
+        return BEMFFT_ENOMEM;
+    }
+    std::vector<int> perm(m);
+    int status = 0;
+    std::vector<double> hu((size_t)nc * m), hr((size_t)nc * m);
+    Cs.assign((size_t)m * nc * nc, 0.0);
+    if (hipMemcpy(perm.data(), p->d_perm, m * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemsetAsync(q, 0, bytes, st) != hipSuccess)
+        status = BEMFFT_EDEVICE;
+    for (int l = 0; l < nc && status == 0; ++l) {
+        std::fill(hu.begin(), hu.end(), 0.0);
+        std::fill(hu.begin() + (size_t)l * m, hu.begin() + (size_t)(l + 1) * m, 1.0);
+        if (hipMemcpyAsync(u, hu.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        status = launch_apply(p, e64, q, u, r, st);
+        if (status) break;
+        if (hipMemcpyAsync(hr.data(), r, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        for (int64_t s = 0; s < m; ++s)
+            for (int k = 0; k < nc; ++k) Cs[((size_t)s * nc + k) * nc + l] = -hr[(size_t)k * m + perm[s]];
+    }
+    dev_free(q);
+    dev_free(u);
+    dev_free(r);
+    if (status == BEMFFT_EDEVICE) set_error("implicit free term: HIP failure");
+    return status;
+}
+
+int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const double *nodes,
+                     const double *normals, const double *weights, int kernel, double nu, double mu,
+                     const bemfft_plan_opts *opts) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (kernel < 0 || kernel > 2) { set_error("unknown kernel"); return BEMFFT_EINVAL; }
+    KindInfo ki = kind_info(kernel);
+    if (grid->dim != ki.dim) { set_error("grid dimension does not match the kernel"); return BEMFFT_EINVAL; }
+    if (m < 1 || m > (int64_t)1 << 30) { set_error("node count out of range"); return BEMFFT_EINVAL; }
+    if (!nodes || !normals) { set_error("nodes and normals are required"); return BEMFFT_EINVAL; }
+    if (!(grid->h > 0.0) || !std::isfinite(grid->h)) { set_error("grid spacing must be positive"); return BEMFFT_EINVAL; }
+    if (kernel == BEMFFT_NAVIER3D && (!(nu > -1.0 && nu < 0.5) || !(mu > 0.0))) {
+        set_error("Navier needs nu in (-1, 1/2) and mu > 0");
+        return BEMFFT_EINVAL;
+    }
+    const int prec = opts ? (int)opts->precision : BEMFFT_FP64;
+    const int cmode = opts ? (int)opts->c_mode : BEMFFT_C_IMPLICIT;
+    if (prec != BEMFFT_FP64 && prec != BEMFFT_FP32) { set_error("unknown precision"); return BEMFFT_EINVAL; }
+    if (cmode < 0 || cmode > 2) { set_error("unknown c_mode"); return BEMFFT_EINVAL; }
+    if (cmode == BEMFFT_C_USER && !(opts && opts->c_user)) { set_error("C_USER needs c_user"); return BEMFFT_EINVAL; }
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    const int d = ki.dim;
+    p->dim = d;
+    p->kernel = kernel;
+    p->cmode = cmode;
+    p->ncomp = ki.ncomp;
+    p->F = ki.F;
+    p->K = ki.K;
+    p->O = ki.O;
+    p->m = m;
+    p->h = grid->h;
+    p->nu = nu;
+    p->mu = mu;
+    for (int a = 0; a < 3; ++a) {
+        p->origin[a] = a < d ? grid->origin[a] : 0.0;
+        p->n[a] = a < d ? grid->n[a] : 1;
+        if (p->n[a] < 1 || p->n[a] > 256) { set_error("grid size per axis must be in [1, 256]"); return BEMFFT_EINVAL; }
+        if (a < d) {
+            int64_t pad = grid->pad[a] ? grid->pad[a] : auto_pad(p->n[a]);
+            if (pad < 2 * p->n[a] - 1 || !fft_size_supported(pad) || pad == 1) {
+                set_error("padded length " + std::to_string(pad) + " on axis " + std::to_string(a) +
+                          " is unsupported or shorter than 2n-1");
+                return BEMFFT_EUNSUPPORTED;
+            }
+            p->P[a] = pad;
+            p->H[a] = pad / 2 + 1;
+        } else {
+            p->P[a] = 1;
+            p->H[a] = 1;
+        }
+    }
+    // snap, validate
+    std::vector<int> g((size_t)m * 3, 0);
+    std::vector<double> w(m), nr((size_t)m * 3, 0.0);
+    for (int64_t j = 0; j < m; ++j) {
+        for (int a = 0; a < d; ++a) {
+            const double x = nodes[j * d + a];
+            const double nv = normals[j * d + a];
+            if (!std::isfinite(x) || !std::isfinite(nv)) { set_error("non-finite node or normal"); return BEMFFT_EINVAL; }
+            const double gi = std::floor((x - p->origin[a]) / p->h + 0.5);
+            if (gi < 0.0 || gi >= (double)p->n[a]) {
+                set_error("node " + std::to_string(j) + " lies outside the grid");
+                return BEMFFT_EINVAL;
+            }
+            g[j * 3 + a] = (int)gi;
+            nr[j * 3 + a] = nv;
+        }
+        w[j] = weights ? weights[j] : std::pow(p->h, d - 1);
+        if (!(w[j] > 0.0) || !std::isfinite(w[j])) { set_error("weights must be positive and finite"); return BEMFFT_EINVAL; }
+    }
+    // sort by (z, y, x): rows of the grid become contiguous runs
+    std::vector<int> perm(m);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+        if (g[a * 3 + 2] != g[b * 3 + 2]) return g[a * 3 + 2] < g[b * 3 + 2];
+        if (g[a * 3 + 1] != g[b * 3 + 1]) return g[a * 3 + 1] < g[b * 3 + 1];
+        return g[a * 3] < g[b * 3];
+    });
+    const int zlo = g[perm[0] * 3 + 2], zhi = g[perm[m - 1] * 3 + 2];
+    p->z0 = zlo;
+    p->nzo = zhi - zlo + 1;
+    const int64_t ny = p->n[1];
+    std::vector<int> rowptr((size_t)p->nzo * ny + 1, 0);
+    std::vector<int> sgx(m), sgy(m), sgz(m);
+    std::vector<double> sw(m), snr((size_t)3 * m);
+    for (int64_t s = 0; s < m; ++s) {
+        const int j = perm[s];
+        sgx[s] = g[j * 3];
+        sgy[s] = g[j * 3 + 1];
+        sgz[s] = g[j * 3 + 2];
+        sw[s] = w[j];
+        for (int a = 0; a < 3; ++a) snr[a * m + s] = nr[j * 3 + a];
+        rowptr[(size_t)(sgz[s] - zlo) * ny + sgy[s] + 1] += 1;
+    }
+    for (size_t i = 1; i < rowptr.size(); ++i) rowptr[i] += rowptr[i - 1];
+    for (int64_t z = 0; z < p->nzo; ++z)
+        p->max_plane_nodes = std::max<int64_t>(p->max_plane_nodes, rowptr[(z + 1) * ny] - rowptr[z * ny]);
+    // per-node free term and self correction blocks (sorted order)
+    const int O = p->O;
+    std::vector<double> C((size_t)m * O * O, 0.0), SC((size_t)m * O * O, 0.0);
+    p->h_diag_dir.assign((size_t)O * m, 0.0);
+    for (int64_t s = 0; s < m; ++s) {
+        double self[9], k0w[9], n3[3] = {snr[s], snr[m + s], snr[2 * m + s]};
+        self_blocks(kernel, sw[s], n3, p->h, nu, mu, self, k0w);
+        for (int i = 0; i < O * O; ++i) SC[(size_t)s * O * O + i] = self[i] - k0w[i];
+        for (int k = 0; k < O; ++k) p->h_diag_dir[(size_t)k * m + perm[s]] = -self[k * O + k];
+    }
+    int st_ = 0;
+    st_ = dev_upload(&p->d_gx, sgx);
+    if (!st_) st_ = dev_upload(&p->d_gy, sgy);
+    if (!st_) st_ = dev_upload(&p->d_gz, sgz);
+    if (!st_) st_ = dev_upload(&p->d_perm, perm);
+    if (!st_) st_ = dev_upload(&p->d_rowptr, rowptr);
+    if (!st_) st_ = dev_upload(&p->d_w, sw);
+    if (!st_) st_ = dev_upload(&p->d_nrm, snr);
+    if (!st_) st_ = dev_upload(&p->d_SC, SC);
+    if (!st_) st_ = dev_upload(&p->d_C, C);  // zero until set below
+    BF_CHECK(st_);
+    // spectra in FP64, and the working-precision engine
+    Engine e64;
+    e64.precision = BEMFFT_FP64;
+    e64.creal = 8;
+    int status = alloc_workspace(p, &e64);
+    if (!status) status = upload_twiddles(&e64, p);
+    if (!status) status = build_spectra(p, &e64, nullptr, st);
+    if (status) { free_engine(&e64); return status; }
+    // free term
+    std::vector<double> Cs;
+    if (cmode == BEMFFT_C_IMPLICIT) {
+        status = implicit_free_term(p, e64, st, Cs);
+        if (status) { free_engine(&e64); return status; }
+    } else {
+        Cs.assign((size_t)m * O * O, 0.0);
+        for (int64_t s = 0; s < m; ++s)
+            for (int k = 0; k < O; ++k)
+                for (int l = 0; l < O; ++l) {
+                    double v;
+                    if (cmode == BEMFFT_C_HALF) v = (k == l) ? 0.5 : 0.0;
+                    else v = opts->c_user[(size_t)perm[s] * O * O + k * O + l];
+                    if (!std::isfinite(v)) { free_engine(&e64); set_error("non-finite c_user"); return BEMFFT_EINVAL; }
+                    Cs[((size_t)s * O + k) * O + l] = v;
+                }
+    }
+    if (hipMemcpy(p->d_C, Cs.data(), Cs.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        free_engine(&e64);
+        set_error("upload of c failed");
+        return BEMFFT_EDEVICE;
+    }
+    p->h_c.assign((size_t)m * O * O, 0.0);
+    p->h_diag_neu.assign((size_t)O * m, 0.0);
+    for (int64_t s = 0; s < m; ++s) {
+        for (int i = 0; i < O * O; ++i) p->h_c[(size_t)perm[s] * O * O + i] = Cs[(size_t)s * O * O + i];
+        for (int k = 0; k < O; ++k) p->h_diag_neu[(size_t)k * m + perm[s]] = Cs[((size_t)s * O + k) * O + k];
+    }
+    if (prec == BEMFFT_FP64) {
+        p->eng = e64;
+    } else {
+        Engine e32;
+        e32.precision = BEMFFT_FP32;
+        e32.creal = 4;
+        status = alloc_workspace(p, &e32);
+        if (!status) status = upload_twiddles(&e32, p);
+        if (!status) {
+            const int64_t n = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2];
+            std::vector<double> tmp(n);
+            std::vector<float> tmpf(n);
+            if (hipMemcpy(tmp.data(), e64.spec, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+                (std::transform(tmp.begin(), tmp.end(), tmpf.begin(), [](double v) { return (float)v; }),
+                 hipMemcpy(e32.spec, tmpf.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)) {
+                status = BEMFFT_EDEVICE;
+                set_error("spectrum conversion failed");
+            }
+        }
+        free_engine(&e64);
+        if (status) { free_engine(&e32); return status; }
+        p->eng = e32;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) { set_error("plan: stream sync failed"); return BEMFFT_EDEVICE; }
+    p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bemfft_plan_create(bemfft_plan **out, const bemfft_grid *grid, int64_t m, const double *nodes,
+                       const double *normals, const double *weights, int kernel, double nu, double mu,
+                       const bemfft_plan_opts *opts) {
+    if (!out || !grid) {
+        set_error("out and grid must be non-null");
+        return BEMFFT_EINVAL;
+    }
+    *out = nullptr;
+    bemfft_plan *p = new (std::nothrow) bemfft_plan();
+    if (!p) {
+        set_error("host allocation failed");
+        return BEMFFT_ENOMEM;
+    }
+    int st = plan_create_impl(p, grid, m, nodes, normals, weights, kernel, nu, mu, opts);
+    if (st) {
+        destroy_plan_state(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return 0;
+}
+
+int bemfft_apply(bemfft_plan *p, const double *q, const double *u, double *r, void *stream) {
+    if (!p || !q || !u || !r) {
+        set_error("apply: null argument");
+        return BEMFFT_EINVAL;
+    }
+    return launch_apply(p, p->eng, q, u, r, (hipStream_t)stream);
+}
+
+int bemfft_apply_profile(bemfft_plan *p, const double *q, const double *u, double *r, int reps,
+                         double *stage_ms, void *stream) {
+    if (!p || !q || !u || !r || !stage_ms || reps < 1) {
+        set_error("apply_profile: bad argument");
+        return BEMFFT_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev[5];
+    for (int i = 0; i < 5; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) {
+            for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+            set_error("hipEventCreate failed");
+            return BEMFFT_EDEVICE;
+        }
+    double acc[4] = {0, 0, 0, 0};
+    int status = 0;
+    for (int it = 0; it < reps && status == 0; ++it) {
+        status = launch_apply(p, p->eng, q, u, r, st, ev);
+        if (status) break;
+        if (hipEventSynchronize(ev[4]) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+            acc[k] += ms;
+        }
+    }
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    if (status == BEMFFT_EDEVICE) set_error("apply_profile: HIP failure");
+    for (int k = 0; k < 4; ++k) stage_ms[k] = acc[k] / reps;
+    return status;
+}
+
+int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {
+    if (!p || !info) {
+        set_error("null argument");
+        return BEMFFT_EINVAL;
+    }
+    std::memset(info, 0, sizeof(*info));
+    info->dim = p->dim;
+    info->kernel = p->kernel;
+    info->precision = p->eng.precision;
+    info->c_mode = p->cmode;
+    info->m = p->m;
+    info->ncomp = p->ncomp;
+    for (int a = 0; a < 3; ++a) {
+        info->n[a] = p->n[a];
+        info->pad[a] = p->P[a];
+    }
+    info->z_lo = p->z0;
+    info->z_count = p->nzo;
+    info->nfields = p->F;
+    info->nspectra = p->K;
+    info->noutputs = p->O;
+    info->workspace_bytes = (int64_t)p->eng.bytes;
+    info->spectra_bytes = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2] * (int64_t)p->eng.creal;
+    info->spectrum_parity_residual = p->parity_resid;
+    info->plan_seconds = p->plan_seconds;
+    return 0;
+}
+
+int bemfft_plan_get_c(const bemfft_plan *p, double *c_host) {
+    if (!p || !c_host) {
+        set_error("null argument");
+        return BEMFFT_EINVAL;
+    }
+    std::memcpy(c_host, p->h_c.data(), p->h_c.size() * sizeof(double));
+    return 0;
+}
+
+int bemfft_plan_destroy(bemfft_plan *p) {
+    if (!p) return 0;
+    destroy_plan_state(p);
+    delete p;
+    return 0;
+}
+
+int bemfft_fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int direction, void *stream) {
+    if (!data || (direction != 1 && direction != -1)) {
+        set_error("fft3d: bad argument");
+        return BEMFFT_EINVAL;
+    }
+    return fft3d_c2c_f64(data, px, py, pz, direction, (hipStream_t)stream);
+}
+
+const char *bemfft_strerror(int status) {
+    switch (status) {
+        case BEMFFT_OK: return "ok";
+        case BEMFFT_EINVAL: return "invalid argument";
+        case BEMFFT_ENOMEM: return "out of memory";
+        case BEMFFT_EDEVICE: return "HIP runtime error";
+        case BEMFFT_EUNSUPPORTED: return "unsupported size";
+        case BEMFFT_EBREAKDOWN: return "breakdown (non-finite values)";
+        case BEMFFT_ENOCONV: return "not converged within maxit";
+        default: return "unknown status";
+    }
+}
+
+const char *bemfft_last_error(void) { return g_last_error.c_str(); }
+
+int bemfft_supported_sizes(int64_t *sizes, int cap) {
+    int n = (int)(sizeof(kSizes) / sizeof(kSizes[0]));
+    for (int i = 0; i < n && i < cap; ++i) sizes[i] = kSizes[i];
+    return n;
+}
+
+}  // extern "C"

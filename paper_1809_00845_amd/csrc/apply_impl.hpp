@@ -1,0 +1,493 @@
+// apply_impl.hpp -- the hot path: r = c u + D[u] - S[q] as the zero-padded
+// FFT convolution of eq. (16), in four kernels.
+//
+//   k_fwd_xy   per occupied z-plane and chunk of kx: scatter of the boundary
+//              fields (Fig. 4) fused with their x-transform, done as a direct
+//              DFT over the few nodes of each grid row (the field is zero
+//              elsewhere), then the y-FFT in LDS.   -> Y[f][kx][z][ky]
+//   k_zpass    per (kx, tile of ky): forward z-FFT of every field (input zero
+//              outside the occupied planes), products with the compact kernel
+//              spectra summed into each output (eqs. 15-16), inverse z-FFT,
+//              keep the occupied planes.              -> Z[o][kx][z][ky]
+//   k_inv_yx   per occupied z-plane and chunk of kx: inverse y-FFT in LDS, then
+//              the inverse x-transform evaluated only at the plane's nodes
+//              ("the values of interest lie only on the boundary", Sec. 4);
+//              one partial sum per chunk.              -> partial[g][o][node]
+//   k_epilogue per node: sum of the chunks + c u + self-term correction.
+//
+// Layout: complex intermediates are interleaved (re, im) in the working
+// precision R with ky contiguous, so every global access is a run of whole
+// rows; kernel spectra are [c][kx][ky][kz] reals over one octant.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft_device.hpp"
+#include "internal.hpp"
+#include "kinds.hpp"
+
+namespace bemfft {
+
+struct ApplyArgs {
+    int nx, ny, nz;
+    int px, py, pz;
+    int hx, hy, hz;
+    int z0, nzo;
+    int m;
+    int G;
+    int node_splits;  // node chunks per plane in the gather
+    const int *gx, *gy, *rowptr, *perm;
+    const double *w, *nrm, *C, *SC;
+    const double *q, *u;
+    double *r;
+    const void *spec, *twx, *twy, *twz;
+    void *vf;  // [F][m] boundary fields in sorted order, working precision
+    void *Y, *Z;
+    double *partial;
+};
+
+constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+constexpr int mini(int a, int b) { return a < b ? a : b; }
+constexpr int kMaxPx = 512;          // largest padded length along x
+constexpr int kGatherChunk = 2048;   // nodes per gather block
+
+// (k x) mod p for 0 <= k x < 2^24, with a float estimate of the quotient.
+__device__ __forceinline__ int mod_small(int kx, int x, int p, float inv_p) {
+    const int prod = kx * x;
+    int r = prod - (int)((float)prod * inv_p) * p;
+    if (r < 0) r += p;
+    if (r >= p) r -= p;
+    return r;
+}
+
+// ------------------------------------------------------------------ k_fields
+// Boundary fields of every node in sorted order (the zero-extended data of
+// Fig. 4 before it is placed on the grid): Laplace q w and u n_i w;
+// Navier t_j w and the symmetrised u (x) n w.
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_fields(ApplyArgs a) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.m) return;
+    R *vf = static_cast<R *>(a.vf);
+    const int j = a.perm[s];
+    const double wt = a.w[s];
+    const double n[3] = {a.nrm[s], a.nrm[a.m + s], a.nrm[2 * a.m + s]};
+    if constexpr (KIND == 0 || KIND == 1) {
+        const double uw = a.u[j] * wt;
+        vf[s] = (R)(a.q[j] * wt);
+#pragma unroll
+        for (int i = 0; i < (KIND == 0 ? 2 : 3); ++i) vf[(1 + i) * a.m + s] = (R)(uw * n[i]);
+    } else {
+        double uu[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vf[c * a.m + s] = (R)(a.q[c * a.m + j] * wt);
+            uu[c] = a.u[c * a.m + j];
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = pair_i(p), k = pair_j(p);
+            const double v = (i == k ? uu[i] * n[i] : uu[i] * n[k] + uu[k] * n[i]) * wt;
+            vf[(3 + p) * a.m + s] = (R)v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ k_fwd_xy
+template <typename R, int PY, int KIND>
+struct FwdCfg {
+    static constexpr int F = Terms<KIND>::F;
+    static constexpr int TPP = PencilShape<PY>::TPP;
+    static constexpr int CB = (int)sizeof(cx<R>);
+    static constexpr int KXC = clampi(mini(256 / (F * TPP), (64 * 1024 - (PY + kMaxPx) * CB) / (F * PY * CB)), 1, 4);
+    static constexpr int NT = F * KXC * TPP;
+};
+
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
+    using Cfg = FwdCfg<R, PY, KIND>;
+    constexpr int F = Cfg::F, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP;
+    __shared__ cx<R> buf[F * KXC * PY];
+    __shared__ cx<R> tw[PY];
+    __shared__ cx<R> twx[kMaxPx];
+    const int tid = threadIdx.x;
+    const int kx0 = blockIdx.x * KXC;
+    const int zz = blockIdx.y;
+    const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
+    const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
+    const R *vf = static_cast<const R *>(a.vf);
+    for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
+    for (int i = tid; i < a.px; i += NT) twx[i] = gtwx[i];
+    __syncthreads();
+    const float inv_px = 1.0f / (float)a.px;
+    // x-transform of the zero-extended fields, row by row: a direct DFT over
+    // the row's nodes (a row of the grid holds few of them).  Every row
+    // y < ny is written, so the buffer needs no clearing.
+    for (int pr = tid; pr < KXC * a.ny; pr += NT) {
+        const int kxl = pr % KXC, y = pr / KXC, kx = kx0 + kxl;
+        if (kx >= a.hx) continue;
+        const int s0 = a.rowptr[zz * a.ny + y], s1 = a.rowptr[zz * a.ny + y + 1];
+        cx<R> acc[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) acc[f] = {R(0), R(0)};
+        for (int s = s0; s < s1; ++s) {
+            const cx<R> w = twx[mod_small(kx, a.gx[s], a.px, inv_px)];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const R vv = vf[f * a.m + s];
+                acc[f].x += vv * w.x;
+                acc[f].y += vv * w.y;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) buf[(f * KXC + kxl) * PY + y] = acc[f];
+    }
+    __syncthreads();
+    pencil_fft<R, PY, -1>(buf + (tid / TPP) * PY, tw, tid % TPP, 0, a.ny);
+    __syncthreads();
+    cx<R> *Y = static_cast<cx<R> *>(a.Y);
+    for (int i = tid; i < F * KXC * PY; i += NT) {
+        const int pen = i / PY, e = i % PY;
+        const int f = pen / KXC, kx = kx0 + pen % KXC;
+        if (kx < a.hx) Y[((size_t)(f * a.hx + kx) * a.nzo + zz) * PY + e] = buf[i];
+    }
+}
+
+// ------------------------------------------------------------------ k_zpass
+template <typename R, int PZ, int KIND>
+struct ZCfg {
+    static constexpr int TPP = PencilShape<PZ>::TPP;
+    static constexpr int CB = (int)sizeof(cx<R>);
+    static constexpr int TY = clampi(mini(256 / TPP, (64 * 1024 - PZ * CB) / (PZ * CB)), 1, 16);
+    static constexpr int NT = TY * TPP;
+    static constexpr int E = PZ / TPP;
+    static constexpr int L = E / 2;  // tile elements per thread (occupied planes <= PZ/2)
+};
+
+// Kernel spectrum value for component c at (kx, ky, kz) from the octant
+// store, with the reflection sign of each odd axis.
+template <typename R, int KIND>
+__device__ __forceinline__ R spec_at(const R *spec, const ApplyArgs &a, int c, int kx, int ky, int kz) {
+    const int mask = comp_oddmask(KIND, c);
+    const int kyp = ky < a.hy ? ky : a.py - ky;
+    const int kzp = kz < a.hz ? kz : a.pz - kz;
+    R s = spec[(((size_t)c * a.hx + kx) * a.hy + kyp) * a.hz + kzp];
+    const bool flip = ((ky >= a.hy) && (mask & 2)) != ((kz >= a.hz) && (mask & 4));
+    return flip ? -s : s;
+}
+
+template <typename R>
+__device__ __forceinline__ void mac(cx<R> &acc, cx<R> v, R s, bool imag) {
+    if (imag) {  // (i s) v
+        acc.x -= s * v.y;
+        acc.y += s * v.x;
+    } else {
+        acc.x += s * v.x;
+        acc.y += s * v.y;
+    }
+}
+
+template <typename R, int PZ, int KIND>
+__global__ __launch_bounds__((ZCfg<R, PZ, KIND>::NT)) void k_zpass(ApplyArgs a) {
+    using Cfg = ZCfg<R, PZ, KIND>;
+    using T = Terms<KIND>;
+    constexpr int TY = Cfg::TY, NT = Cfg::NT, TPP = Cfg::TPP, E = Cfg::E, L = Cfg::L;
+    constexpr int F = T::F, O = T::O;
+    constexpr bool kPrefetchSpec = (T::N == T::F);  // one spectrum per field
+    __shared__ cx<R> buf[TY * PZ];
+    __shared__ cx<R> tw[PZ];
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x;
+    const int ky0 = blockIdx.y * TY;
+    const int b = tid / TPP, t = tid % TPP;
+    const int ky = ky0 + b;
+    const bool live = ky < a.py;
+    const cx<R> *twz = static_cast<const cx<R> *>(a.twz);
+    const cx<R> *Y = static_cast<const cx<R> *>(a.Y);
+    cx<R> *Z = static_cast<cx<R> *>(a.Z);
+    const R *spec = static_cast<const R *>(a.spec);
+    for (int i = tid; i < PZ; i += NT) tw[i] = twz[i];
+    const int nrow = a.nzo * TY;
+
+    // tile of one field: rows z0..z0+nzo-1 of TY consecutive ky, kept in
+    // registers so that the next field's loads overlap this field's FFT
+    cx<R> pre[L];
+    auto load_tile = [&](int f) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int i = tid + l * NT;
+            const int zz = i / TY, bb = i % TY;
+            pre[l] = (i < nrow && ky0 + bb < a.py)
+                         ? Y[((size_t)(f * a.hx + kx) * a.nzo + zz) * a.py + ky0 + bb]
+                         : cx<R>{R(0), R(0)};
+        }
+    };
+    load_tile(0);
+    cx<R> acc[O][E];
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[o][e] = {R(0), R(0)};
+
+    static_for<0, F>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
+        R kv[kPrefetchSpec ? E : 1];
+        if constexpr (kPrefetchSpec) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) kv[e] = live ? spec_at<R, KIND>(spec, a, f, kx, ky, t + e * TPP) : R(0);
+        }
+        __syncthreads();  // everyone is done with the previous field's pencils
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int i = tid + l * NT;
+            if (i < nrow) buf[(i % TY) * PZ + a.z0 + i / TY] = pre[l];
+        }
+        if constexpr (f + 1 < F) load_tile(f + 1);
+        __syncthreads();
+        pencil_fft<R, PZ, -1>(buf + b * PZ, tw, t, a.z0, a.z0 + a.nzo);
+        if (live) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int kz = t + e * TPP;
+                const cx<R> v = buf[b * PZ + kz];
+                if constexpr (kPrefetchSpec) {
+                    mac<R>(acc[0][e], v, kv[e], comp_imag(KIND, f));
+                } else {
+                    static_for<0, T::N>([&](auto tc) {
+                        constexpr int term = decltype(tc)::value;
+                        if constexpr (T::f(term) == f) {
+                            constexpr int c = T::c(term);
+                            mac<R>(acc[T::o(term)][e], v, spec_at<R, KIND>(spec, a, c, kx, ky, kz),
+                                   comp_imag(KIND, c));
+                        }
+                    });
+                }
+            }
+        }
+    });
+
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf[b * PZ + t + e * TPP] = acc[o][e];
+        pencil_fft<R, PZ, 1>(buf + b * PZ, tw, t);
+        __syncthreads();
+        for (int i = tid; i < nrow; i += NT) {
+            const int zz = i / TY, bb = i % TY;
+            if (ky0 + bb < a.py)
+                Z[((size_t)(o * a.hx + kx) * a.nzo + zz) * a.py + ky0 + bb] = buf[bb * PZ + a.z0 + zz];
+        }
+    }
+}
+
+// 2D: the third axis has length 1, so the "z pass" is the spectral product.
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_mac2d(ApplyArgs a) {
+    using T = Terms<KIND>;
+    constexpr int O = T::O;
+    const int kx = blockIdx.x;
+    const int ky = blockIdx.y * 256 + threadIdx.x;
+    if (ky >= a.py) return;
+    const cx<R> *Y = static_cast<const cx<R> *>(a.Y);
+    cx<R> *Z = static_cast<cx<R> *>(a.Z);
+    const R *spec = static_cast<const R *>(a.spec);
+    cx<R> acc[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) acc[o] = {R(0), R(0)};
+    static_for<0, T::N>([&](auto tc) {
+        constexpr int term = decltype(tc)::value;
+        constexpr int c = T::c(term), o = T::o(term), f = T::f(term);
+        const cx<R> v = Y[(size_t)(f * a.hx + kx) * a.py + ky];
+        mac<R>(acc[o], v, spec_at<R, KIND>(spec, a, c, kx, ky, 0), comp_imag(KIND, c));
+    });
+#pragma unroll
+    for (int o = 0; o < O; ++o) Z[(size_t)(o * a.hx + kx) * a.py + ky] = acc[o];
+}
+
+// ------------------------------------------------------------------ k_inv_yx
+template <typename R, int PY, int KIND>
+struct InvCfg {
+    static constexpr int O = Terms<KIND>::O;
+    static constexpr int TPP = PencilShape<PY>::TPP;
+    static constexpr int CB = (int)sizeof(cx<R>);
+    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - (PY + kMaxPx) * CB) / (O * PY * CB)), 1, 16);
+    static constexpr int NT = O * KXC * TPP;
+};
+
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs a) {
+    using Cfg = InvCfg<R, PY, KIND>;
+    constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP;
+    __shared__ cx<R> buf[O * KXC * PY];
+    __shared__ cx<R> tw[PY];
+    __shared__ cx<R> twx[kMaxPx];
+    const int tid = threadIdx.x;
+    const int g = blockIdx.x;
+    const int kx0 = g * KXC;
+    const int zz = blockIdx.y;
+    // this block's share of the plane's nodes; empty shares leave at once
+    const int p0 = a.rowptr[zz * a.ny], p1 = a.rowptr[(zz + 1) * a.ny];
+    const int s0 = p0 + blockIdx.z * kGatherChunk;
+    const int s1 = min(p1, s0 + kGatherChunk);
+    if (s0 >= s1) return;
+    const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
+    const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
+    const cx<R> *Z = static_cast<const cx<R> *>(a.Z);
+    for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
+    for (int i = tid; i < a.px; i += NT) twx[i] = gtwx[i];
+    for (int i = tid; i < O * KXC * PY; i += NT) {
+        const int pen = i / PY, e = i % PY;
+        const int o = pen / KXC, kx = kx0 + pen % KXC;
+        buf[i] = (kx < a.hx) ? Z[((size_t)(o * a.hx + kx) * a.nzo + zz) * PY + e] : cx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    pencil_fft<R, PY, 1>(buf + (tid / TPP) * PY, tw, tid % TPP);
+    __syncthreads();
+    const float inv_px = 1.0f / (float)a.px;
+    const int nk = min(KXC, a.hx - kx0);
+    for (int s = s0 + tid; s < s1; s += NT) {
+        const int y = a.gy[s], x = a.gx[s];
+        double acc[O];
+#pragma unroll
+        for (int o = 0; o < O; ++o) acc[o] = 0.0;
+        int idx = mod_small(kx0, x, a.px, inv_px);  // (kx x) mod px, stepped below
+        for (int kxl = 0; kxl < nk; ++kxl) {
+            const int kx = kx0 + kxl;
+            const cx<R> w = twx[idx];
+            const double cf = (kx == 0 || 2 * kx == a.px) ? 1.0 : 2.0;
+#pragma unroll
+            for (int o = 0; o < O; ++o) {
+                const cx<R> v = buf[(o * KXC + kxl) * PY + y];
+                acc[o] += cf * (double)(v.x * w.x + v.y * w.y);  // Re(v conj(w))
+            }
+            idx += x;
+            if (idx >= a.px) idx -= a.px;
+        }
+#pragma unroll
+        for (int o = 0; o < O; ++o) a.partial[((size_t)g * O + o) * a.m + s] = acc[o];
+    }
+}
+
+// ------------------------------------------------------------------ epilogue
+template <int O>
+__global__ __launch_bounds__(256) void k_epilogue(ApplyArgs a) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.m) return;
+    const int j = a.perm[s];
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+        double v = 0.0;
+        for (int g = 0; g < a.G; ++g) v += a.partial[((size_t)g * O + o) * a.m + s];
+#pragma unroll
+        for (int l = 0; l < O; ++l) {
+            v += a.C[((size_t)s * O + o) * O + l] * a.u[l * a.m + j];
+            v -= a.SC[((size_t)s * O + o) * O + l] * a.q[l * a.m + j];
+        }
+        a.r[o * a.m + j] = v;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename R, int PY, int KIND>
+int launch_fwd(const ApplyArgs &a, hipStream_t st) {
+    using Cfg = FwdCfg<R, PY, KIND>;
+    dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
+    hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+    BF_HIP(hipGetLastError());
+    return 0;
+}
+template <typename R, int PY, int KIND>
+int launch_inv(const ApplyArgs &a, hipStream_t st) {
+    using Cfg = InvCfg<R, PY, KIND>;
+    dim3 grid(a.G, a.nzo, a.node_splits);
+    hipLaunchKernelGGL((k_inv_yx<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+    BF_HIP(hipGetLastError());
+    return 0;
+}
+template <typename R, int PZ, int KIND>
+int launch_z(const ApplyArgs &a, hipStream_t st) {
+    if constexpr (PZ == 1) {
+        dim3 grid(a.hx, (a.py + 255) / 256);
+        hipLaunchKernelGGL((k_mac2d<R, KIND>), grid, dim3(256), 0, st, a);
+    } else {
+        using Cfg = ZCfg<R, PZ, KIND>;
+        dim3 grid(a.hx, (a.py + Cfg::TY - 1) / Cfg::TY);
+        hipLaunchKernelGGL((k_zpass<R, PZ, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+    }
+    BF_HIP(hipGetLastError());
+    return 0;
+}
+
+#define BF_SIZE_SWITCH(len, FN, ...)                        \
+    switch (len) {                                          \
+        case 32: return FN<32>(__VA_ARGS__);                \
+        case 64: return FN<64>(__VA_ARGS__);                \
+        case 96: return FN<96>(__VA_ARGS__);                \
+        case 128: return FN<128>(__VA_ARGS__);              \
+        case 192: return FN<192>(__VA_ARGS__);              \
+        case 256: return FN<256>(__VA_ARGS__);              \
+        case 320: return FN<320>(__VA_ARGS__);              \
+        case 384: return FN<384>(__VA_ARGS__);              \
+        case 512: return FN<512>(__VA_ARGS__);              \
+        default: break;                                     \
+    }
+
+template <typename R, int KIND>
+struct Launch {
+    template <int P> static int fwd(const ApplyArgs &a, hipStream_t st) { return launch_fwd<R, P, KIND>(a, st); }
+    template <int P> static int inv(const ApplyArgs &a, hipStream_t st) { return launch_inv<R, P, KIND>(a, st); }
+    template <int P> static int z(const ApplyArgs &a, hipStream_t st) { return launch_z<R, P, KIND>(a, st); }
+    template <int P> static int kxc(int) { return InvCfg<R, P, KIND>::KXC; }
+
+    // ev (optional): five events recorded around the four stages.
+    static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
+        if (ev) BF_HIP(hipEventRecord(ev[0], st));
+        hipLaunchKernelGGL((k_fields<R, KIND>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);
+        BF_CHECK(dispatch_fwd(a, st));
+        if (ev) BF_HIP(hipEventRecord(ev[1], st));
+        BF_CHECK(dispatch_z(a, st));
+        if (ev) BF_HIP(hipEventRecord(ev[2], st));
+        BF_CHECK(dispatch_inv(a, st));
+        if (ev) BF_HIP(hipEventRecord(ev[3], st));
+        hipLaunchKernelGGL((k_epilogue<Terms<KIND>::O>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);
+        BF_HIP(hipGetLastError());
+        if (ev) BF_HIP(hipEventRecord(ev[4], st));
+        return 0;
+    }
+    static int dispatch_fwd(const ApplyArgs &a, hipStream_t st) {
+        BF_SIZE_SWITCH(a.py, fwd, a, st);
+        set_error("unsupported y length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    static int dispatch_inv(const ApplyArgs &a, hipStream_t st) {
+        BF_SIZE_SWITCH(a.py, inv, a, st);
+        set_error("unsupported y length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    static int dispatch_z(const ApplyArgs &a, hipStream_t st) {
+        if constexpr (KIND == 0) {
+            if (a.pz == 1) return z<1>(a, st);
+            set_error("2D plans need pz == 1");
+            return BEMFFT_EUNSUPPORTED;
+        } else {
+            BF_SIZE_SWITCH(a.pz, z, a, st);
+            set_error("unsupported z length");
+            return BEMFFT_EUNSUPPORTED;
+        }
+    }
+    static int inv_kxc(int py) {
+        BF_SIZE_SWITCH(py, kxc, 0);
+        return 0;
+    }
+};
+
+// Per-family entry points, instantiated in one source file per family.
+template <int KIND>
+int apply_kind(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t *ev);
+template <int KIND>
+int inv_kxc_kind(int precision, int py);
+
+}  // namespace bemfft

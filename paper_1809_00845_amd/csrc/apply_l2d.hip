@@ -1,0 +1,18 @@
+// apply_l2d.hip -- instantiation of the hot path for kernel family 0.
+#include "apply_impl.hpp"
+
+namespace bemfft {
+
+template <>
+int apply_kind<0>(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t *ev) {
+    if (precision == BEMFFT_FP32) return Launch<float, 0>::run(a, st, ev);
+    return Launch<double, 0>::run(a, st, ev);
+}
+
+template <>
+int inv_kxc_kind<0>(int precision, int py) {
+    if (precision == BEMFFT_FP32) return Launch<float, 0>::inv_kxc(py);
+    return Launch<double, 0>::inv_kxc(py);
+}
+
+}  // namespace bemfft

@@ -1,0 +1,18 @@
+// apply_l3d.hip -- instantiation of the hot path for kernel family 1.
+#include "apply_impl.hpp"
+
+namespace bemfft {
+
+template <>
+int apply_kind<1>(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t *ev) {
+    if (precision == BEMFFT_FP32) return Launch<float, 1>::run(a, st, ev);
+    return Launch<double, 1>::run(a, st, ev);
+}
+
+template <>
+int inv_kxc_kind<1>(int precision, int py) {
+    if (precision == BEMFFT_FP32) return Launch<float, 1>::inv_kxc(py);
+    return Launch<double, 1>::inv_kxc(py);
+}
+
+}  // namespace bemfft

@@ -1,0 +1,18 @@
+// apply_nav.hip -- instantiation of the hot path for kernel family 2.
+#include "apply_impl.hpp"
+
+namespace bemfft {
+
+template <>
+int apply_kind<2>(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t *ev) {
+    if (precision == BEMFFT_FP32) return Launch<float, 2>::run(a, st, ev);
+    return Launch<double, 2>::run(a, st, ev);
+}
+
+template <>
+int inv_kxc_kind<2>(int precision, int py) {
+    if (precision == BEMFFT_FP32) return Launch<float, 2>::inv_kxc(py);
+    return Launch<double, 2>::inv_kxc(py);
+}
+
+}  // namespace bemfft

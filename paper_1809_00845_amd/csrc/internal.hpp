@@ -1,0 +1,114 @@
+// internal.hpp -- plan layout and launchers shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bemfft.h"
+
+namespace bemfft {
+
+// Thread-local error message (bemfft_last_error).
+void set_error(const std::string &msg);
+
+#define BF_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::bemfft::set_error(std::string(#call) + ": " + hipGetErrorString(e_));  \
+            return BEMFFT_EDEVICE;                                                    \
+        }                                                                             \
+    } while (0)
+
+#define BF_CHECK(st)                \
+    do {                            \
+        int s_ = (st);              \
+        if (s_ < 0) return s_;      \
+    } while (0)
+
+// Fields, spectra and outputs of each kernel family (the integrals of
+// eqs. 14-15 for Laplace; eq. 8 written with Kelvin's tensors for Navier).
+//   Laplace 2D: fields q w, u n_x w, u n_y w; spectra u*, d_x u*, d_y u*.
+//   Laplace 3D: fields q w, u n_i w (3);      spectra u*, d_i u* (3).
+//   Navier:     fields t_j w (3), s_(ij) w (6, symmetric u (x) n);
+//               spectra U_(kj) (6), Sigma_k,(ij) (18).
+struct KindInfo {
+    int dim, ncomp, F, K, O;
+};
+inline KindInfo kind_info(int kernel) {
+    switch (kernel) {
+        case BEMFFT_LAPLACE2D: return {2, 1, 3, 3, 1};
+        case BEMFFT_LAPLACE3D: return {3, 1, 4, 4, 1};
+        default: return {3, 3, 9, 24, 3};
+    }
+}
+
+// Device state of one working precision.
+struct Engine {
+    int precision = BEMFFT_FP64;  // BEMFFT_FP64 or BEMFFT_FP32
+    size_t creal = 8;             // bytes per real
+    void *spec = nullptr;         // [K][Hx][Hy][Hz] reals
+    void *twx = nullptr;          // [Px] complex, exp(-2 pi i t / Px)
+    void *twy = nullptr;          // [Py]
+    void *twz = nullptr;          // [Pz]
+    void *Y = nullptr;            // [F][Hx][nzo][Py] complex
+    void *Z = nullptr;            // [O][Hx][nzo][Py] complex
+    double *partial = nullptr;    // [G][O][m]
+    void *vf = nullptr;           // [F][m] sorted boundary fields
+    int G = 0;                    // kx chunks of the inverse pass
+    size_t bytes = 0;
+};
+
+}  // namespace bemfft
+
+struct bemfft_plan {
+    int dim = 0, kernel = 0, cmode = 0;
+    int ncomp = 1, F = 0, K = 0, O = 0;
+    int64_t m = 0;
+    int64_t n[3] = {1, 1, 1};
+    int64_t P[3] = {1, 1, 1};
+    int64_t H[3] = {1, 1, 1};
+    int64_t z0 = 0, nzo = 1;
+    int64_t max_plane_nodes = 0;  // largest node count of one grid plane
+    double h = 0.0, nu = 0.0, mu = 0.0;
+    double origin[3] = {0, 0, 0};
+    // node arrays in sorted order (z, y, x)
+    int *d_gx = nullptr, *d_gy = nullptr, *d_gz = nullptr;
+    int *d_perm = nullptr;     // sorted slot -> caller's node index
+    int *d_rowptr = nullptr;   // [nzo * ny + 1] start of each (z, y) row
+    double *d_w = nullptr;     // [m]
+    double *d_nrm = nullptr;   // [3][m]
+    double *d_C = nullptr;     // [m][O][O] free term
+    double *d_SC = nullptr;    // [m][O][O] self-term correction (exact - grid)
+    bemfft::Engine eng;        // working precision
+    std::vector<double> h_c;   // c values in caller order (m or 9 m)
+    std::vector<double> h_diag_dir, h_diag_neu;  // Jacobi entries per slot
+    double parity_resid = 0.0;
+    double plan_seconds = 0.0;
+    // solve workspace, allocated on first use
+    double *s_V = nullptr;
+    int s_cap = 0;
+    double *s_vec = nullptr;   // misc vectors
+    double *s_red = nullptr;   // reduction scratch
+    double *s_hbuf = nullptr;  // device copy of Hessenberg column / coefficients
+    double *h_pinned = nullptr;
+};
+
+namespace bemfft {
+
+// Apply-stage launchers (apply.hip).
+int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double *u, double *r,
+                 hipStream_t st, hipEvent_t *ev = nullptr);
+// Spectrum precompute (spectra.hip): fills e64 (FP64) and, if e32 is
+// non-null, its rounded FP32 copy.
+int build_spectra(bemfft_plan *p, Engine *e64, Engine *e32, hipStream_t st);
+int fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int dir, hipStream_t st);
+bool fft_size_supported(int64_t n);
+int upload_twiddles(Engine *e, const bemfft_plan *p);
+int alloc_workspace(bemfft_plan *p, Engine *e);
+void free_engine(Engine *e);
+
+}  // namespace bemfft

@@ -1,0 +1,271 @@
+// spectra.hip -- kernel sampling on the padded grid and its FP64 transform.
+//
+// "The three kernel functions ... are roughly approximated on constant
+// elements on the entire parameter space which is extended for the
+// application of the FFT" (Sec. 4, Fig. 5).  Reading used here: the kernel
+// is point-sampled at every padded-grid offset m (m_a in [-P_a/2, P_a/2)),
+// with the flat-panel value at m = 0 for the single layer (0 for the odd
+// double-layer kernels) and 0 on the planes m_a = -P_a/2, which no pair of
+// nodes reaches and whose zeroing keeps odd kernels exactly odd.  The
+// transform is FP64 always; one octant of the real (or imaginary) spectrum is
+// kept, because each kernel is even or odd along every axis.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fft_device.hpp"
+#include "internal.hpp"
+#include "kinds.hpp"
+
+namespace bemfft {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Kernel component c of family 'kernel' at offset xi (physical units), FP64.
+__device__ double kernel_value(int kernel, int c, double x, double y, double z, double nu, double mu) {
+    double r2 = x * x + y * y + z * z;
+    double r = sqrt(r2);
+    if (kernel == BEMFFT_LAPLACE2D) {
+        if (c == 0) return -log(r) / (2.0 * kPi);         // eq. (3)
+        double a = (c == 1) ? x : y;
+        return -a / (2.0 * kPi * r2);                      // eq. (12), gradient of u*
+    }
+    if (kernel == BEMFFT_LAPLACE3D) {
+        if (c == 0) return 1.0 / (4.0 * kPi * r);
+        double a = (c == 1) ? x : ((c == 2) ? y : z);
+        return -a / (4.0 * kPi * r2 * r);
+    }
+    double xi[3] = {x, y, z};
+    if (c < 6) {  // Kelvin displacement tensor, eq. (7)
+        int k = pair_i(c), j = pair_j(c);
+        double v = xi[k] * xi[j] / (r2 * r);
+        if (k == j) v += (3.0 - 4.0 * nu) / r;
+        return v / (16.0 * kPi * mu * (1.0 - nu));
+    }
+    // Kelvin stress tensor: the stress of the fundamental displacement
+    int k = (c - 6) / 6, p = (c - 6) % 6;
+    int i = pair_i(p), j = pair_j(p);
+    double e[3] = {x / r, y / r, z / r};
+    double a = 1.0 - 2.0 * nu;
+    double v = a * ((k == i ? e[j] : 0.0) + (k == j ? e[i] : 0.0) - (i == j ? e[k] : 0.0)) + 3.0 * e[i] * e[j] * e[k];
+    return -v / (8.0 * kPi * (1.0 - nu) * r2);
+}
+
+// Grid value at offset 0: flat-panel integral over the reference measure
+// h^(d-1), per unit measure.  Navier: panel orientation averaged (<n n> = I/3).
+double kernel_k0(int kernel, int c, double h, double nu, double mu) {
+    const double l = std::log(1.0 + std::sqrt(2.0));
+    if (kernel == BEMFFT_LAPLACE2D) return c == 0 ? (1.0 - std::log(0.5 * h)) / (2.0 * kPi) : 0.0;
+    if (kernel == BEMFFT_LAPLACE3D) return c == 0 ? l / (kPi * h) : 0.0;
+    if (c < 3) return (4.0 * l / h) * ((3.0 - 4.0 * nu) + 1.0 / 3.0) / (16.0 * kPi * mu * (1.0 - nu));
+    return 0.0;
+}
+
+__global__ void k_sample(cx<double> *out, int64_t px, int64_t py, int64_t pz, int kernel, int c,
+                         double h, double nu, double mu, double k0, double scale) {
+    int64_t total = px * py * pz;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t ix = idx % px, iy = (idx / px) % py, iz = idx / (px * py);
+        bool nyq = (px > 1 && 2 * ix == px) || (py > 1 && 2 * iy == py) || (pz > 1 && 2 * iz == pz);
+        int64_t mx = (2 * ix < px) ? ix : ix - px;
+        int64_t my = (2 * iy < py) ? iy : iy - py;
+        int64_t mz = (2 * iz < pz) ? iz : iz - pz;
+        double v;
+        if (nyq) v = 0.0;
+        else if (mx == 0 && my == 0 && mz == 0) v = k0;
+        else v = kernel_value(kernel, c, h * (double)mx, h * (double)my, h * (double)mz, nu, mu);
+        out[idx] = {scale * v, 0.0};
+    }
+}
+
+// Pencils per block of the FP64 axis pass: at most 16, 256 threads and 64 KB of LDS.
+template <int P>
+constexpr int axis_batch() {
+    int b = 16;
+    if (256 / PencilShape<P>::TPP < b) b = 256 / PencilShape<P>::TPP;
+    int lds = (64 * 1024 - P * 16) / (P * 16);
+    if (lds < b) b = lds;
+    return b < 1 ? 1 : b;
+}
+
+// Batched FFT along one axis of a [pz][py][px] complex FP64 array.  A block
+// takes B pencils adjacent in memory along the fastest other axis, so that
+// global loads and stores are coalesced; the pencils are transformed in LDS.
+template <int P, int DIR>
+__global__ void k_fft_axis(cx<double> *data, int axis, int64_t px, int64_t py, int64_t pz) {
+    using S = PencilShape<P>;
+    constexpr int B = axis_batch<P>();
+    constexpr int NT = B * S::TPP;
+    __shared__ cx<double> buf[B * P];
+    __shared__ cx<double> tw[P];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P; i += NT) {
+        ctrig::CS w = ctrig::cs2pi(i, P);  // exact quadrant reduction
+        tw[i] = {w.c, -w.s};
+    }
+    int64_t npen, stride;
+    if (axis == 0) { npen = py * pz; stride = 1; }
+    else if (axis == 1) { npen = px * pz; stride = px; }
+    else { npen = px * py; stride = px * py; }
+    const int64_t pid0 = (int64_t)blockIdx.x * B;
+    auto base_of = [&](int64_t pid) -> int64_t {
+        if (axis == 0) return pid * px;
+        if (axis == 1) return (pid / px) * py * px + (pid % px);
+        return pid;  // (y * px + x)
+    };
+    for (int i = tid; i < B * P; i += NT) {
+        int b, e;
+        if (axis == 0) { b = i / P; e = i % P; } else { e = i / B; b = i % B; }
+        int64_t pid = pid0 + b;
+        buf[b * P + e] = (pid < npen) ? data[base_of(pid) + e * stride] : cx<double>{0.0, 0.0};
+    }
+    __syncthreads();
+    pencil_fft<double, P, DIR>(buf + (tid / S::TPP) * P, tw, tid % S::TPP);
+    __syncthreads();
+    for (int i = tid; i < B * P; i += NT) {
+        int b, e;
+        if (axis == 0) { b = i / P; e = i % P; } else { e = i / B; b = i % B; }
+        int64_t pid = pid0 + b;
+        if (pid < npen) data[base_of(pid) + e * stride] = buf[b * P + e];
+    }
+}
+
+template <int P>
+int launch_axis(cx<double> *d, int axis, int64_t px, int64_t py, int64_t pz, int dir, hipStream_t st) {
+    using S = PencilShape<P>;
+    constexpr int B = axis_batch<P>();
+    int64_t npen = (axis == 0) ? py * pz : (axis == 1 ? px * pz : px * py);
+    dim3 grid((unsigned)((npen + B - 1) / B)), block(B * S::TPP);
+    if (dir < 0) hipLaunchKernelGGL((k_fft_axis<P, -1>), grid, block, 0, st, d, axis, px, py, pz);
+    else hipLaunchKernelGGL((k_fft_axis<P, 1>), grid, block, 0, st, d, axis, px, py, pz);
+    BF_HIP(hipGetLastError());
+    return 0;
+}
+
+int axis_pass(cx<double> *d, int axis, int64_t len, int64_t px, int64_t py, int64_t pz, int dir, hipStream_t st) {
+    switch (len) {
+        case 1: return 0;
+        case 32: return launch_axis<32>(d, axis, px, py, pz, dir, st);
+        case 64: return launch_axis<64>(d, axis, px, py, pz, dir, st);
+        case 96: return launch_axis<96>(d, axis, px, py, pz, dir, st);
+        case 128: return launch_axis<128>(d, axis, px, py, pz, dir, st);
+        case 192: return launch_axis<192>(d, axis, px, py, pz, dir, st);
+        case 256: return launch_axis<256>(d, axis, px, py, pz, dir, st);
+        case 320: return launch_axis<320>(d, axis, px, py, pz, dir, st);
+        case 384: return launch_axis<384>(d, axis, px, py, pz, dir, st);
+        case 512: return launch_axis<512>(d, axis, px, py, pz, dir, st);
+        default:
+            set_error("FFT length " + std::to_string(len) + " is not supported");
+            return BEMFFT_EUNSUPPORTED;
+    }
+}
+
+// Positive doubles order like their bit patterns: max via 64-bit atomics.
+__device__ void atomic_max_pos(unsigned long long *dst, double v) {
+    atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_extract(const cx<double> *full, double *out, int64_t px, int64_t py, int64_t hx,
+                          int64_t hy, int64_t hz, int imag, unsigned long long *stats) {
+    int64_t total = hx * hy * hz;
+    double kept = 0.0, disc = 0.0;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t kz = idx % hz, ky = (idx / hz) % hy, kx = idx / (hz * hy);
+        cx<double> v = full[(kz * py + ky) * px + kx];
+        double a = imag ? v.y : v.x;
+        double b = imag ? v.x : v.y;
+        out[idx] = a;
+        kept = fmax(kept, fabs(a));
+        disc = fmax(disc, fabs(b));
+    }
+    atomic_max_pos(stats + 0, kept);
+    atomic_max_pos(stats + 1, disc);
+}
+
+__global__ void k_to_f32(const double *in, float *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+}  // namespace
+
+bool fft_size_supported(int64_t n) {
+    switch (n) {
+        case 1: case 32: case 64: case 96: case 128: case 192: case 256: case 320: case 384: case 512:
+            return true;
+        default:
+            return false;
+    }
+}
+
+int fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int dir, hipStream_t st) {
+    if (!fft_size_supported(px) || !fft_size_supported(py) || !fft_size_supported(pz)) {
+        set_error("fft3d: unsupported length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    cx<double> *d = reinterpret_cast<cx<double> *>(data);
+    BF_CHECK(axis_pass(d, 0, px, px, py, pz, dir, st));
+    BF_CHECK(axis_pass(d, 1, py, px, py, pz, dir, st));
+    BF_CHECK(axis_pass(d, 2, pz, px, py, pz, dir, st));
+    return 0;
+}
+
+int build_spectra(bemfft_plan *p, Engine *e64, Engine *e32, hipStream_t st) {
+    const int64_t px = p->P[0], py = p->P[1], pz = p->P[2];
+    const int64_t hx = p->H[0], hy = p->H[1], hz = p->H[2];
+    const int64_t full_n = px * py * pz;
+    const int64_t oct = hx * hy * hz;
+    cx<double> *full = nullptr;
+    unsigned long long *stats = nullptr;
+    BF_HIP(hipMalloc(&full, full_n * sizeof(cx<double>)));
+    if (hipMalloc(&stats, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipFree(full);
+        set_error("hipMalloc(stats) failed");
+        return BEMFFT_ENOMEM;
+    }
+    double worst = 0.0;
+    int status = 0;
+    const double scale = -1.0 / (double)full_n;
+    for (int c = 0; c < p->K && status == 0; ++c) {
+        double k0 = kernel_k0(p->kernel, c, p->h, p->nu, p->mu);
+        int blocks = (int)std::min<int64_t>((full_n + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(256), 0, st, full, px, py, pz, p->kernel, c, p->h,
+                           p->nu, p->mu, k0, scale);
+        if (hipGetLastError() != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        status = fft3d_c2c_f64(reinterpret_cast<double *>(full), px, py, pz, -1, st);
+        if (status) break;
+        if (hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        double *dst = static_cast<double *>(e64->spec) + (int64_t)c * oct;
+        int eb = (int)std::min<int64_t>((oct + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_extract, dim3(eb), dim3(256), 0, st, full, dst, px, py, hx, hy, hz,
+                           comp_imag(p->kernel, c) ? 1 : 0, stats);
+        unsigned long long hs[2];
+        if (hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        double kept, disc;
+        std::memcpy(&kept, &hs[0], 8);
+        std::memcpy(&disc, &hs[1], 8);
+        if (kept > 0.0) worst = std::max(worst, disc / kept);
+    }
+    if (status == 0 && e32) {
+        int64_t n = (int64_t)p->K * oct;
+        int eb = (int)std::min<int64_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_to_f32, dim3(eb), dim3(256), 0, st, static_cast<const double *>(e64->spec),
+                           static_cast<float *>(e32->spec), n);
+        if (hipGetLastError() != hipSuccess) status = BEMFFT_EDEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess && status == 0) status = BEMFFT_EDEVICE;
+    (void)hipFree(full);
+    (void)hipFree(stats);
+    if (status == BEMFFT_EDEVICE) set_error("spectrum precompute: HIP failure");
+    p->parity_resid = worst;
+    return status;
+}
+
+}  // namespace bemfft

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar (normwise, scale = |c u| + sum |D||u| + sum |S||q| per node, computed by
+the oracle): 1e-12 in FP64.  FP32: 2e-5, derived from the FP32 round-off of
+O(log P) transform stages and the spectral products relative to the term
+magnitudes (measured ~1e-6).  Integer work (snapping, sorting, row pointers)
+is exact by construction and shows up as FP64 parity at 1e-12.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_1809_00845_amd import binding as B  # noqa: E402
+from paper_1809_00845_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.FP64: 1e-12, B.FP32: 2e-5}
+ORC_KIND = {B.LAPLACE2D: O.LAPLACE2D, B.LAPLACE3D: O.LAPLACE3D, B.NAVIER3D: O.NAVIER3D}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), device=dev)
+
+
+def _parity(dev, g, kernel, precision, cmode=B.C_IMPLICIT, seed=0, cuser=None, nu=0.3, mu=1.0, targets=None):
+    nc = 3 if kernel == B.NAVIER3D else 1
+    m = len(g.weights)
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(-1, 1, (nc, m))
+    u = rng.uniform(-1, 1, (nc, m))
+    plan = B.Plan(g, kernel, precision=precision, c_mode=cmode, c_user=cuser, nu=nu, mu=mu)
+    r = plan.apply(_t(q, dev), _t(u, dev))
+    torch.cuda.synchronize()
+    r = r.cpu().numpy().reshape(nc, m)
+    p = O.problem(g, ORC_KIND[kernel], nu, mu)
+    ref, sc = O.apply(p, q if nc > 1 else q[0], u if nc > 1 else u[0], cmode=cmode, cuser=cuser,
+                      with_scale=True, targets=targets)
+    ref = np.reshape(ref, (nc, -1))
+    t0, t1 = targets or (0, m)
+    err = np.abs(r[:, t0:t1] - ref).max() / np.max(sc)
+    info = plan.info()
+    plan.close()
+    return err, info
+
+
+# ------------------------------------------------------------------ transforms
+
+
+@pytest.mark.parametrize("shape", [(32, 1, 1), (64, 32, 1), (96, 1, 1), (128, 64, 1), (192, 1, 1),
+                                   (256, 32, 1), (320, 1, 1), (384, 1, 1), (512, 1, 1), (32, 64, 96)])
+def test_fft3d_vs_numpy(dev, shape):
+    px, py, pz = shape
+    rng = np.random.default_rng(1)
+    a = rng.normal(size=(pz, py, px)) + 1j * rng.normal(size=(pz, py, px))
+    t = torch.tensor(np.stack([a.real, a.imag], -1).reshape(-1), device=dev)
+    B.bemfft_fft3d_c2c_f64(t, px, py, pz, -1)
+    got = t.cpu().numpy().reshape(pz, py, px, 2)
+    ref = np.fft.fftn(a)
+    err = np.abs(got[..., 0] + 1j * got[..., 1] - ref).max() / np.abs(ref).max()
+    assert err < 1e-14
+    B.bemfft_fft3d_c2c_f64(t, px, py, pz, 1)
+    back = t.cpu().numpy().reshape(pz, py, px, 2)
+    err2 = np.abs((back[..., 0] + 1j * back[..., 1]) / (px * py * pz) - a).max() / np.abs(a).max()
+    assert err2 < 1e-14
+
+
+# ------------------------------------------------------------------ Laplace 2D
+
+
+@pytest.mark.parametrize("cmode", [B.C_IMPLICIT, B.C_HALF, B.C_USER])
+def test_laplace2d_circle_parity(dev, cmode):
+    g = I.circle2d(32, 0.3)
+    cuser = np.random.default_rng(3).uniform(0.2, 0.8, g.m) if cmode == B.C_USER else None
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.LAPLACE2D, prec, cmode, cuser=cuser)
+        assert err < TOL[prec], (prec, err)
+        assert info["spectrum_parity_residual"] < 1e-14
+
+
+def test_laplace2d_config1_parity(dev):
+    """Circle R = 0.4 on 128^2, padded 256^2 (~400 nodes)."""
+    g = I.circle2d(128, 0.4)
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.LAPLACE2D, prec)
+        assert info["pad"][:2] == [256, 256]
+        assert err < TOL[prec], (prec, err)
+
+
+def test_laplace2d_square_and_shuffled_order(dev):
+    g = I.square2d(64, 40).permuted(7)
+    for prec in (B.FP64, B.FP32):
+        err, _ = _parity(dev, g, B.LAPLACE2D, prec)
+        assert err < TOL[prec]
+
+
+# ------------------------------------------------------------------ Laplace 3D
+
+
+@pytest.mark.parametrize("n", [16, 32, 48])
+def test_laplace3d_sphere_parity(dev, n):
+    """Sizes with P = 32, 64, 96 (several tiles, ragged last ky tile in FP64)."""
+    g = I.sphere3d(n, 0.35)
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.LAPLACE3D, prec)
+        assert err < TOL[prec], (n, prec, err)
+    assert info["spectrum_parity_residual"] < 1e-14
+
+
+def test_laplace3d_cube_parity_all_cmodes(dev):
+    g = I.cube3d(32, 20)
+    for cmode in (B.C_IMPLICIT, B.C_HALF):
+        for prec in (B.FP64, B.FP32):
+            err, _ = _parity(dev, g, B.LAPLACE3D, prec, cmode)
+            assert err < TOL[prec]
+
+
+def test_laplace3d_ragged_grid(dev):
+    """Unequal axes (n = 40 x 24 x 20, pads 96 x 64 x 64) and a shape that
+    touches only a few planes and rows: most rows are empty."""
+    rng = np.random.default_rng(5)
+    gi = np.stack([rng.integers(3, 37, 300), rng.integers(2, 22, 300), rng.integers(8, 13, 300)], 1)
+
+    class G:
+        pass
+
+    g = G()
+    g.dim, g.n, g.h, g.origin = 3, (40, 24, 20), 1.0 / 40, (0.0, 0.0, 0.0)
+    g.nodes = gi * g.h
+    nv = rng.normal(size=(300, 3))
+    g.normals = nv / np.linalg.norm(nv, axis=1, keepdims=True)
+    g.weights = rng.uniform(0.2, 1.5, 300) * g.h ** 2
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.LAPLACE3D, prec)
+        assert info["pad"] == [96, 64, 64]
+        assert err < TOL[prec], (prec, err)
+
+
+def test_single_node_and_duplicates(dev):
+    """One node (only its self term and c); then nodes sharing a cell."""
+    class G:
+        pass
+
+    g = G()
+    g.dim, g.n, g.h, g.origin = 3, (16, 16, 16), 1 / 16, (0.0, 0.0, 0.0)
+    g.nodes = np.array([[0.5, 0.25, 0.75]])
+    g.normals = np.array([[0.0, 0.0, 1.0]])
+    g.weights = np.array([0.003])
+    err, _ = _parity(dev, g, B.LAPLACE3D, B.FP64, B.C_HALF)
+    assert err < 1e-12
+    g.nodes = np.array([[0.5, 0.25, 0.75], [0.51, 0.26, 0.74], [0.25, 0.25, 0.25]])
+    g.normals = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    g.weights = np.array([0.003, 0.002, 0.004])
+    err, _ = _parity(dev, g, B.LAPLACE3D, B.FP64, B.C_HALF)
+    assert err < 1e-12
+
+
+# ------------------------------------------------------------------ Navier
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_navier_sphere_parity(dev, n):
+    g = I.sphere3d(n, 0.35)
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.NAVIER3D, prec, nu=0.3, mu=1.0)
+        assert err < TOL[prec], (prec, err)
+    assert info["nspectra"] == 24
+
+
+def test_navier_cube_user_c(dev):
+    g = I.cube3d(16, 10)
+    cuser = np.tile((0.5 * np.eye(3)).reshape(1, 9), (g.m, 1))
+    err, _ = _parity(dev, g, B.NAVIER3D, B.FP64, B.C_USER, cuser=cuser, nu=0.25, mu=2.0)
+    assert err < 1e-12
+
+
+# ------------------------------------------------------------------ full size
+
+
+def test_config2_sphere_full_size_sampled(dev):
+    """Sphere R = 0.35 on 128^3, padded 256^3: all outputs from the GPU,
+    a contiguous sample of 600 targets from the oracle."""
+    g = I.sphere3d(128, 0.35)
+    for prec in (B.FP32, B.FP64):
+        err, info = _parity(dev, g, B.LAPLACE3D, prec, targets=(5000, 5600))
+        assert info["pad"] == [256, 256, 256]
+        assert err < TOL[prec], (prec, err)
+
+
+def test_config2_cube_full_size_sampled(dev):
+    g = I.cube3d(128, 100)
+    assert g.m == 58808
+    err, _ = _parity(dev, g, B.LAPLACE3D, B.FP32, targets=(0, 400))
+    assert err < TOL[B.FP32]
+
+
+def test_apply_is_deterministic(dev):
+    g = I.sphere3d(48, 0.35)
+    rng = np.random.default_rng(2)
+    q = _t(rng.uniform(-1, 1, g.m), dev)
+    u = _t(rng.uniform(-1, 1, g.m), dev)
+    plan = B.Plan(g, B.LAPLACE3D, precision=B.FP32)
+    r1 = plan.apply(q, u).clone()
+    r2 = plan.apply(q, u)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2)
+
+
+# ------------------------------------------------------------------ solves
+
+
+def test_config1_dirichlet_solve(dev):
+    """Sec. 4 problem on the circle: u = x^2 - y^2 given, q sought, GMRES to
+    1e-10; against the oracle's LU solution and the analytic flux."""
+    g = I.circle2d(128, 0.4)
+    u, q_exact = I.harmonic_2d_x2y2(g)
+    bc = np.zeros(g.m, dtype=np.uint8)
+    plan = B.Plan(g, B.LAPLACE2D, precision=B.FP64)
+    x, info = plan.solve(_t(bc, dev), _t(u, dev), tol=1e-10, restart=200, maxit=2000)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-10
+    x = x.cpu().numpy()
+    p = O.problem(g, O.LAPLACE2D)
+    xl = O.solve_lu(p, bc, u)
+    assert np.linalg.norm(x - xl) / np.linalg.norm(xl) < 1e-6
+    w = g.weights
+    assert math.sqrt(np.sum(w * (x - q_exact) ** 2) / np.sum(w * q_exact ** 2)) < 0.12
+
+
+def test_mixed_sphere_solve(dev):
+    g = I.sphere3d(32, 0.35)
+    u, q = I.harmonic_3d_xyz(g)
+    bc = I.mixed_bc_upper(g)
+    known = np.where(bc == 0, u, q)
+    plan = B.Plan(g, B.LAPLACE3D, precision=B.FP64)
+    x, info = plan.solve(_t(bc, dev), _t(known, dev), tol=1e-10)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-10
+    xl = O.solve_lu(O.problem(g, O.LAPLACE3D), bc, known)
+    assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
+
+
+def test_navier_mixed_solve(dev):
+    g = I.sphere3d(16, 0.35)
+    nu, mu = 0.3, 1.0
+    lam = 2 * mu * nu / (1 - 2 * nu)
+    E = np.random.default_rng(4).normal(size=(3, 3))
+    Es = 0.5 * (E + E.T)
+    u = (g.rel() @ E.T).T
+    t = (g.normals @ (lam * np.trace(Es) * np.eye(3) + 2 * mu * Es).T).T
+    bc = np.tile(I.mixed_bc_upper(g), (3, 1))
+    known = np.where(bc == 0, u, t)
+    plan = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=nu, mu=mu)
+    x, info = plan.solve(_t(bc, dev), _t(known, dev), tol=1e-10)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-10
+    xl = O.solve_lu(O.problem(g, O.NAVIER3D, nu, mu), bc, known)
+    assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
+
+
+def test_solve_maxit_reports_noconv(dev):
+    g = I.circle2d(64, 0.4)
+    u, _ = I.harmonic_2d_x2y2(g)
+    bc = np.zeros(g.m, dtype=np.uint8)
+    plan = B.Plan(g, B.LAPLACE2D)
+    x, info = plan.solve(_t(bc, dev), _t(u, dev), tol=1e-14, maxit=3)
+    assert info["status"] == B.ENOCONV and info["iters"] == 3
+    assert np.isfinite(x.cpu().numpy()).all()

@@ -1,0 +1,89 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function the header declares, and rejects bad arguments before any
+device work starts."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1809_00845_amd import binding as B
+from paper_1809_00845_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "bemfft.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bemfft_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_1809_00845_amd import build
+
+        build.build()
+    return B.load()
+
+
+def test_header_symbols_exported(lib):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(B.EXPORTS) == set(names)
+
+
+def test_strerror_and_sizes(lib):
+    assert B.strerror(0) == "ok"
+    assert "invalid" in B.strerror(B.EINVAL)
+    assert B.supported_sizes() == [32, 64, 96, 128, 192, 256, 320, 384, 512]
+
+
+def _expect(status_fn, code):
+    with pytest.raises(B.BemfftError) as ei:
+        status_fn()
+    assert ei.value.status == code
+
+
+def test_plan_validation_rejects_before_device_work(lib):
+    g = I.circle2d(32, 0.3)
+    # kernel / dimension mismatch
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE3D), B.EINVAL)
+    # node off the grid
+    bad = g.nodes.copy()
+    bad[3, 0] = 1.5
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, bad, g.normals, g.weights, B.LAPLACE2D), B.EINVAL)
+    # non-positive weight
+    w = g.weights.copy()
+    w[0] = 0.0
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, w, B.LAPLACE2D), B.EINVAL)
+    # non-finite coordinate
+    nn = g.nodes.copy()
+    nn[1, 1] = np.nan
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, nn, g.normals, g.weights, B.LAPLACE2D), B.EINVAL)
+    # padded length shorter than 2n - 1 / not a supported length
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
+                                         pad=(32, 64, 0)), B.EUNSUPPORTED)
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
+                                         pad=(66, 64, 0)), B.EUNSUPPORTED)
+    # Navier material parameters
+    s = I.cube3d(16, 8)
+    _expect(lambda: B.bemfft_plan_create(3, s.n, s.h, s.nodes, s.normals, s.weights, B.NAVIER3D, nu=0.5),
+            B.EINVAL)
+    _expect(lambda: B.bemfft_plan_create(3, s.n, s.h, s.nodes, s.normals, s.weights, B.NAVIER3D, mu=0.0),
+            B.EINVAL)
+    # C_USER without values
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
+                                         c_mode=B.C_USER), B.EINVAL)
+
+
+def test_null_arguments(lib):
+    assert lib.bemfft_apply(None, None, None, None, None) == B.EINVAL
+    assert lib.bemfft_solve(None, None, None, None, None, None, None) == B.EINVAL
+    assert lib.bemfft_plan_destroy(None) == 0
+    assert lib.bemfft_plan_get_info(None, None) == B.EINVAL
