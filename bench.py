@@ -153,6 +153,8 @@ def main():
         dts = timed_applies(psph, qsd, usd, rs, args.steps, 5)
         extra["sphere_nodes"] = sph.m
         extra["sphere_fp32_matvec_s"] = args.steps / dts
+        extra["sphere_stage_ms"] = dict(zip(names, B.bemfft_apply_profile(psph.handle, qsd, usd, rs, reps=50)))
+        extra["cube_fp64_stage_ms"] = dict(zip(names, B.bemfft_apply_profile(plan64.handle, q, u, r, reps=20)))
         # time to solve, mixed BC, 1e-6 true relative residual
         solves = {}
         for name, g, pl32, pl64 in (("cube", cube, plan, plan64), ("sphere", sph, psph, None)):

@@ -20,6 +20,8 @@ namespace {
 thread_local std::string g_last_error;
 constexpr double kPi = 3.141592653589793238462643383279502884;
 const int64_t kSizes[] = {32, 64, 96, 128, 192, 256, 320, 384, 512};
+// A grid row holding this many nodes is x-transformed by FFT.
+constexpr int kDenseRow = 24;
 
 template <typename T>
 int dev_upload(T **dst, const std::vector<T> &src) {
@@ -94,6 +96,7 @@ void free_engine(Engine *e) {
     dev_free(e->Z);
     dev_free(e->partial);
     dev_free(e->vf);
+    dev_free(e->Xd);
     *e = Engine{};
 }
 
@@ -132,13 +135,14 @@ int alloc_workspace(bemfft_plan *p, Engine *e) {
     const size_t ysz = (size_t)p->F * rows * cb, zsz = (size_t)p->O * rows * cb;
     const size_t psz = (size_t)e->G * p->O * p->m * sizeof(double);
     const size_t vsz = (size_t)p->F * p->m * e->creal;
+    const size_t xsz = std::max<size_t>(1, (size_t)p->nd * p->F * p->H[0] * cb);
     if (hipMalloc(&e->spec, spec) != hipSuccess || hipMalloc(&e->Y, ysz) != hipSuccess ||
         hipMalloc(&e->Z, zsz) != hipSuccess || hipMalloc(&e->partial, psz) != hipSuccess ||
-        hipMalloc(&e->vf, vsz) != hipSuccess) {
+        hipMalloc(&e->vf, vsz) != hipSuccess || hipMalloc(&e->Xd, xsz) != hipSuccess) {
         set_error("hipMalloc of the workspace failed");
         return BEMFFT_ENOMEM;
     }
-    e->bytes = spec + ysz + zsz + psz + vsz;
+    e->bytes = spec + ysz + zsz + psz + vsz + xsz;
     return 0;
 }
 
@@ -177,6 +181,10 @@ int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double 
     a.Z = e.Z;
     a.partial = e.partial;
     a.vf = e.vf;
+    a.Xd = e.Xd;
+    a.row_dense = p->d_row_dense;
+    a.dense_rows = p->d_dense_rows;
+    a.nd = (int)p->nd;
     a.node_splits = (int)std::max<int64_t>(1, (p->max_plane_nodes + kGatherChunk - 1) / kGatherChunk);
     if (p->kernel == 0) return apply_kind<0>(e.precision, a, st, ev);
     if (p->kernel == 1) return apply_kind<1>(e.precision, a, st, ev);
@@ -200,6 +208,8 @@ void destroy_plan_state(bemfft_plan *p) {
     dev_free(p->d_nrm);
     dev_free(p->d_C);
     dev_free(p->d_SC);
+    dev_free(p->d_row_dense);
+    dev_free(p->d_dense_rows);
     dev_free(p->s_V);
     dev_free(p->s_vec);
     dev_free(p->s_red);
@@ -340,8 +350,19 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
         rowptr[(size_t)(sgz[s] - zlo) * ny + sgy[s] + 1] += 1;
     }
     for (size_t i = 1; i < rowptr.size(); ++i) rowptr[i] += rowptr[i - 1];
-    for (int64_t z = 0; z < p->nzo; ++z)
+    // long rows get their x-transform from a row FFT
+    std::vector<int> row_dense((size_t)p->nzo * ny, -1), dense_rows;
+    for (int64_t z = 0; z < p->nzo; ++z) {
         p->max_plane_nodes = std::max<int64_t>(p->max_plane_nodes, rowptr[(z + 1) * ny] - rowptr[z * ny]);
+        for (int64_t y = 0; y < ny; ++y) {
+            const int64_t row = z * ny + y;
+            if (rowptr[row + 1] - rowptr[row] >= kDenseRow) {
+                row_dense[row] = (int)dense_rows.size();
+                dense_rows.push_back((int)row);
+            }
+        }
+    }
+    p->nd = (int64_t)dense_rows.size();
     // per-node free term and self correction blocks (sorted order)
     const int O = p->O;
     std::vector<double> C((size_t)m * O * O, 0.0), SC((size_t)m * O * O, 0.0);
@@ -362,6 +383,8 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     if (!st_) st_ = dev_upload(&p->d_nrm, snr);
     if (!st_) st_ = dev_upload(&p->d_SC, SC);
     if (!st_) st_ = dev_upload(&p->d_C, C);  // zero until set below
+    if (!st_) st_ = dev_upload(&p->d_row_dense, row_dense);
+    if (!st_ && !dense_rows.empty()) st_ = dev_upload(&p->d_dense_rows, dense_rows);
     BF_CHECK(st_);
     // spectra in FP64, and the working-precision engine
     Engine e64;

@@ -44,6 +44,10 @@ struct ApplyArgs {
     double *r;
     const void *spec, *twx, *twy, *twz;
     void *vf;  // [F][m] boundary fields in sorted order, working precision
+    void *Xd;  // [nd][F][hx] transforms of the long rows
+    const int *row_dense;   // [nzo * ny]: index into dense_rows, or -1
+    const int *dense_rows;  // [nd]: row index (zz * ny + y) of each long row
+    int nd;
     void *Y, *Z;
     double *partial;
 };
@@ -95,21 +99,80 @@ __global__ __launch_bounds__(256) void k_fields(ApplyArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ k_rows_fft
+// Long grid rows (e.g. rows of a box face lying in a grid plane) are
+// x-transformed with an FFT instead of the direct sum: the row's nodes are
+// placed on a zero pencil (nodes sharing a cell are summed in order) and
+// transformed; kx < Hx is kept.                          -> Xd[d][f][kx]
+template <typename R, int PX, int KIND>
+struct RowCfg {
+    static constexpr int TPP = PencilShape<PX>::TPP;
+    static constexpr int PPB = 256 / TPP;  // pencils per block
+};
+
+template <typename R, int PX, int KIND>
+__global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
+    using Cfg = RowCfg<R, PX, KIND>;
+    constexpr int TPP = Cfg::TPP, PPB = Cfg::PPB, E = PX / TPP, PS = pstride<PX>();
+    constexpr int F = Terms<KIND>::F;
+    __shared__ cx<R> buf[PPB * PS];
+    __shared__ cx<R> tw[PX];
+    const int tid = threadIdx.x;
+    const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
+    const R *vf = static_cast<const R *>(a.vf);
+    for (int i = tid; i < PX; i += 256) tw[i] = gtwx[i];
+    const int pen = tid / TPP, t = tid % TPP;
+    const int pid = blockIdx.x * PPB + pen;  // (dense row, field)
+    const int d = pid / F, f = pid % F;
+    const bool live = d < a.nd;
+    cx<R> *pb = buf + pen * PS;
+#pragma unroll
+    for (int e = 0; e < E; ++e) pb[pslot(t + e * TPP)] = {R(0), R(0)};
+    wave_lds_sync();
+    if (live) {
+        const int row = a.dense_rows[d];
+        const int s0 = a.rowptr[row], s1 = a.rowptr[row + 1];
+        for (int s = s0 + t; s < s1; s += TPP) {
+            const int x = a.gx[s];
+            if (s > s0 && a.gx[s - 1] == x) continue;  // summed by the first node of the cell
+            R v = vf[f * a.m + s];
+            for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) v += vf[f * a.m + s2];
+            pb[pslot(x)] = {v, R(0)};
+        }
+    }
+    __syncthreads();  // twiddle table
+    cx<R> xr[E];
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) xr[e] = pb[pslot(t + e * TPP)];
+    fft_regs<R, PX, -1>(xr, pb, tw, t);
+    if (live) {
+        cx<R> *Xd = static_cast<cx<R> *>(a.Xd);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int kx = t + e * TPP;
+            if (kx < a.hx) Xd[((size_t)d * F + f) * a.hx + kx] = xr[e];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ k_fwd_xy
 template <typename R, int PY, int KIND>
 struct FwdCfg {
     static constexpr int F = Terms<KIND>::F;
     static constexpr int TPP = PencilShape<PY>::TPP;
     static constexpr int CB = (int)sizeof(cx<R>);
-    static constexpr int KXC = clampi(mini(256 / (F * TPP), (64 * 1024 - (PY + kMaxPx) * CB) / (F * PY * CB)), 1, 4);
+    static constexpr int PS = pstride<PY>();
+    static constexpr int FIXED = (PY + kMaxPx) * CB;
+    static constexpr int KXC = clampi(mini(256 / (F * TPP), (64 * 1024 - FIXED) / (F * PS * CB)), 1, 4);
     static constexpr int NT = F * KXC * TPP;
 };
 
 template <typename R, int PY, int KIND>
 __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
     using Cfg = FwdCfg<R, PY, KIND>;
-    constexpr int F = Cfg::F, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP;
-    __shared__ cx<R> buf[F * KXC * PY];
+    constexpr int F = Cfg::F, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
+    __shared__ cx<R> buf[F * KXC * PS];
     __shared__ cx<R> tw[PY];
     __shared__ cx<R> twx[kMaxPx];
     const int tid = threadIdx.x;
@@ -118,52 +181,76 @@ __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs 
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
     const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
     const R *vf = static_cast<const R *>(a.vf);
+    const cx<R> *Xd = static_cast<const cx<R> *>(a.Xd);
     for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
     for (int i = tid; i < a.px; i += NT) twx[i] = gtwx[i];
     __syncthreads();
     const float inv_px = 1.0f / (float)a.px;
-    // x-transform of the zero-extended fields, row by row: a direct DFT over
-    // the row's nodes (a row of the grid holds few of them).  Every row
-    // y < ny is written, so the buffer needs no clearing.
+    // x-transform of the zero-extended fields for rows y < ny: a direct DFT
+    // over the row's few nodes, or the row FFT of a long row
     for (int pr = tid; pr < KXC * a.ny; pr += NT) {
         const int kxl = pr % KXC, y = pr / KXC, kx = kx0 + kxl;
         if (kx >= a.hx) continue;
-        const int s0 = a.rowptr[zz * a.ny + y], s1 = a.rowptr[zz * a.ny + y + 1];
+        const int row = zz * a.ny + y;
+        const int dense = a.row_dense[row];
         cx<R> acc[F];
+        if (dense >= 0) {
 #pragma unroll
-        for (int f = 0; f < F; ++f) acc[f] = {R(0), R(0)};
-        for (int s = s0; s < s1; ++s) {
-            const cx<R> w = twx[mod_small(kx, a.gx[s], a.px, inv_px)];
+            for (int f = 0; f < F; ++f) acc[f] = Xd[((size_t)dense * F + f) * a.hx + kx];
+        } else {
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const R vv = vf[f * a.m + s];
-                acc[f].x += vv * w.x;
-                acc[f].y += vv * w.y;
+            for (int f = 0; f < F; ++f) acc[f] = {R(0), R(0)};
+            const int s0 = a.rowptr[row], s1 = a.rowptr[row + 1];
+#pragma unroll 4
+            for (int s = s0; s < s1; ++s) {
+                const cx<R> w = twx[mod_small(kx, a.gx[s], a.px, inv_px)];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const R vv = vf[f * a.m + s];
+                    acc[f].x += vv * w.x;
+                    acc[f].y += vv * w.y;
+                }
             }
         }
 #pragma unroll
-        for (int f = 0; f < F; ++f) buf[(f * KXC + kxl) * PY + y] = acc[f];
+        for (int f = 0; f < F; ++f) buf[(f * KXC + kxl) * PS + pslot(y)] = acc[f];
     }
     __syncthreads();
-    pencil_fft<R, PY, -1>(buf + (tid / TPP) * PY, tw, tid % TPP, 0, a.ny);
-    __syncthreads();
-    cx<R> *Y = static_cast<cx<R> *>(a.Y);
-    for (int i = tid; i < F * KXC * PY; i += NT) {
-        const int pen = i / PY, e = i % PY;
-        const int f = pen / KXC, kx = kx0 + pen % KXC;
-        if (kx < a.hx) Y[((size_t)(f * a.hx + kx) * a.nzo + zz) * PY + e] = buf[i];
+    // y-FFT in registers (rows y >= ny are zero), stored straight from them
+    const int pen = tid / TPP, t = tid % TPP;
+    const int f = pen / KXC, kx = kx0 + pen % KXC;
+    cx<R> *pb = buf + pen * PS;
+    cx<R> x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int y = t + e * TPP;
+        x[e] = y < a.ny ? pb[pslot(y)] : cx<R>{R(0), R(0)};
+    }
+    fft_regs<R, PY, -1>(x, pb, tw, t);
+    if (kx < a.hx) {
+        cx<R> *Y = static_cast<cx<R> *>(a.Y) + ((size_t)(f * a.hx + kx) * a.nzo + zz) * PY;
+#pragma unroll
+        for (int e = 0; e < E; ++e) Y[t + e * TPP] = x[e];
     }
 }
 
 // ------------------------------------------------------------------ k_zpass
+// One wavefront owns PPW = 64/TPP pencils (consecutive ky at one kx) from
+// load to store; waves never wait for each other, so the loads of one wave
+// overlap the transforms of the others.  Lane t of a pencil loads the rows
+// its first FFT stage needs straight into registers, multiplies the
+// transformed values in registers, and stores the inverse transform's rows
+// from registers: LDS only carries the exchange between FFT stages.
 template <typename R, int PZ, int KIND>
 struct ZCfg {
     static constexpr int TPP = PencilShape<PZ>::TPP;
+    static constexpr int PPW = 64 / TPP;
     static constexpr int CB = (int)sizeof(cx<R>);
-    static constexpr int TY = clampi(mini(256 / TPP, (64 * 1024 - PZ * CB) / (PZ * CB)), 1, 16);
-    static constexpr int NT = TY * TPP;
+    static constexpr int PS = pstride<PZ>();
+    static constexpr int WAVES = clampi((64 * 1024) / (PPW * PS * CB), 1, 4);
+    static constexpr int TY = PPW * WAVES;
+    static constexpr int NT = 64 * WAVES;
     static constexpr int E = PZ / TPP;
-    static constexpr int L = E / 2;  // tile elements per thread (occupied planes <= PZ/2)
 };
 
 // Kernel spectrum value for component c at (kx, ky, kz) from the octant
@@ -193,38 +280,21 @@ template <typename R, int PZ, int KIND>
 __global__ __launch_bounds__((ZCfg<R, PZ, KIND>::NT)) void k_zpass(ApplyArgs a) {
     using Cfg = ZCfg<R, PZ, KIND>;
     using T = Terms<KIND>;
-    constexpr int TY = Cfg::TY, NT = Cfg::NT, TPP = Cfg::TPP, E = Cfg::E, L = Cfg::L;
+    constexpr int PPW = Cfg::PPW, TY = Cfg::TY, NT = Cfg::NT, TPP = Cfg::TPP, E = Cfg::E, PS = Cfg::PS;
     constexpr int F = T::F, O = T::O;
-    constexpr bool kPrefetchSpec = (T::N == T::F);  // one spectrum per field
-    __shared__ cx<R> buf[TY * PZ];
+    __shared__ cx<R> buf[TY * PS];
     __shared__ cx<R> tw[PZ];
     const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
     const int kx = blockIdx.x;
-    const int ky0 = blockIdx.y * TY;
-    const int b = tid / TPP, t = tid % TPP;
-    const int ky = ky0 + b;
+    const int b = lane / TPP, t = lane % TPP;
+    const int ky = blockIdx.y * TY + wave * PPW + b;
     const bool live = ky < a.py;
+    cx<R> *pb = buf + (wave * PPW + b) * PS;
     const cx<R> *twz = static_cast<const cx<R> *>(a.twz);
-    const cx<R> *Y = static_cast<const cx<R> *>(a.Y);
-    cx<R> *Z = static_cast<cx<R> *>(a.Z);
     const R *spec = static_cast<const R *>(a.spec);
     for (int i = tid; i < PZ; i += NT) tw[i] = twz[i];
-    const int nrow = a.nzo * TY;
-
-    // tile of one field: rows z0..z0+nzo-1 of TY consecutive ky, kept in
-    // registers so that the next field's loads overlap this field's FFT
-    cx<R> pre[L];
-    auto load_tile = [&](int f) {
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const int i = tid + l * NT;
-            const int zz = i / TY, bb = i % TY;
-            pre[l] = (i < nrow && ky0 + bb < a.py)
-                         ? Y[((size_t)(f * a.hx + kx) * a.nzo + zz) * a.py + ky0 + bb]
-                         : cx<R>{R(0), R(0)};
-        }
-    };
-    load_tile(0);
+    __syncthreads();
     cx<R> acc[O][E];
 #pragma unroll
     for (int o = 0; o < O; ++o)
@@ -233,52 +303,39 @@ __global__ __launch_bounds__((ZCfg<R, PZ, KIND>::NT)) void k_zpass(ApplyArgs a) 
 
     static_for<0, F>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
-        R kv[kPrefetchSpec ? E : 1];
-        if constexpr (kPrefetchSpec) {
+        const cx<R> *Yf = static_cast<const cx<R> *>(a.Y) + (size_t)(f * a.hx + kx) * a.nzo * a.py;
+        cx<R> x[E];
 #pragma unroll
-            for (int e = 0; e < E; ++e) kv[e] = live ? spec_at<R, KIND>(spec, a, f, kx, ky, t + e * TPP) : R(0);
+        for (int e = 0; e < E; ++e) {
+            const int zz = t + e * TPP - a.z0;  // occupied plane index; others are zero
+            x[e] = (live && zz >= 0 && zz < a.nzo) ? Yf[(size_t)zz * a.py + ky] : cx<R>{R(0), R(0)};
         }
-        __syncthreads();  // everyone is done with the previous field's pencils
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            const int i = tid + l * NT;
-            if (i < nrow) buf[(i % TY) * PZ + a.z0 + i / TY] = pre[l];
-        }
-        if constexpr (f + 1 < F) load_tile(f + 1);
-        __syncthreads();
-        pencil_fft<R, PZ, -1>(buf + b * PZ, tw, t, a.z0, a.z0 + a.nzo);
+        fft_regs<R, PZ, -1>(x, pb, tw, t);
         if (live) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int kz = t + e * TPP;
-                const cx<R> v = buf[b * PZ + kz];
-                if constexpr (kPrefetchSpec) {
-                    mac<R>(acc[0][e], v, kv[e], comp_imag(KIND, f));
-                } else {
-                    static_for<0, T::N>([&](auto tc) {
-                        constexpr int term = decltype(tc)::value;
-                        if constexpr (T::f(term) == f) {
-                            constexpr int c = T::c(term);
-                            mac<R>(acc[T::o(term)][e], v, spec_at<R, KIND>(spec, a, c, kx, ky, kz),
-                                   comp_imag(KIND, c));
-                        }
-                    });
-                }
+                static_for<0, T::N>([&](auto tc) {
+                    constexpr int term = decltype(tc)::value;
+                    if constexpr (T::f(term) == f) {
+                        constexpr int c = T::c(term);
+                        mac<R>(acc[T::o(term)][e], x[e], spec_at<R, KIND>(spec, a, c, kx, ky, kz), comp_imag(KIND, c));
+                    }
+                });
             }
         }
     });
 
 #pragma unroll
     for (int o = 0; o < O; ++o) {
-        __syncthreads();
+        fft_regs<R, PZ, 1>(acc[o], pb, tw, t);
+        if (live) {
+            cx<R> *Zo = static_cast<cx<R> *>(a.Z) + (size_t)(o * a.hx + kx) * a.nzo * a.py;
 #pragma unroll
-        for (int e = 0; e < E; ++e) buf[b * PZ + t + e * TPP] = acc[o][e];
-        pencil_fft<R, PZ, 1>(buf + b * PZ, tw, t);
-        __syncthreads();
-        for (int i = tid; i < nrow; i += NT) {
-            const int zz = i / TY, bb = i % TY;
-            if (ky0 + bb < a.py)
-                Z[((size_t)(o * a.hx + kx) * a.nzo + zz) * a.py + ky0 + bb] = buf[bb * PZ + a.z0 + zz];
+            for (int e = 0; e < E; ++e) {
+                const int zz = t + e * TPP - a.z0;
+                if (zz >= 0 && zz < a.nzo) Zo[(size_t)zz * a.py + ky] = acc[o][e];
+            }
         }
     }
 }
@@ -313,15 +370,16 @@ struct InvCfg {
     static constexpr int O = Terms<KIND>::O;
     static constexpr int TPP = PencilShape<PY>::TPP;
     static constexpr int CB = (int)sizeof(cx<R>);
-    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - (PY + kMaxPx) * CB) / (O * PY * CB)), 1, 16);
+    static constexpr int PS = pstride<PY>();
+    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - (PY + kMaxPx) * CB) / (O * PS * CB)), 1, 16);
     static constexpr int NT = O * KXC * TPP;
 };
 
 template <typename R, int PY, int KIND>
 __global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs a) {
     using Cfg = InvCfg<R, PY, KIND>;
-    constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP;
-    __shared__ cx<R> buf[O * KXC * PY];
+    constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
+    __shared__ cx<R> buf[O * KXC * PS];
     __shared__ cx<R> tw[PY];
     __shared__ cx<R> twx[kMaxPx];
     const int tid = threadIdx.x;
@@ -335,39 +393,47 @@ __global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs 
     if (s0 >= s1) return;
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
     const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
-    const cx<R> *Z = static_cast<const cx<R> *>(a.Z);
     for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
     for (int i = tid; i < a.px; i += NT) twx[i] = gtwx[i];
-    for (int i = tid; i < O * KXC * PY; i += NT) {
-        const int pen = i / PY, e = i % PY;
-        const int o = pen / KXC, kx = kx0 + pen % KXC;
-        buf[i] = (kx < a.hx) ? Z[((size_t)(o * a.hx + kx) * a.nzo + zz) * PY + e] : cx<R>{R(0), R(0)};
+    // each pencil row (one output, one kx) is loaded straight into registers
+    const int pen = tid / TPP, t = tid % TPP;
+    const int o = pen / KXC, kx = kx0 + pen % KXC;
+    cx<R> x[E];
+    const cx<R> *Zr = static_cast<const cx<R> *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = kx < a.hx ? Zr[t + e * TPP] : cx<R>{R(0), R(0)};
+    __syncthreads();  // twiddle tables
+    cx<R> *pb = buf + pen * PS;
+    fft_regs<R, PY, 1>(x, pb, tw, t);
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int y = t + e * TPP;
+        if (y < a.ny) pb[pslot(y)] = x[e];
     }
-    __syncthreads();
-    pencil_fft<R, PY, 1>(buf + (tid / TPP) * PY, tw, tid % TPP);
-    __syncthreads();
+    __syncthreads();  // the gather reads every pencil
     const float inv_px = 1.0f / (float)a.px;
     const int nk = min(KXC, a.hx - kx0);
     for (int s = s0 + tid; s < s1; s += NT) {
-        const int y = a.gy[s], x = a.gx[s];
-        double acc[O];
+        const int y = a.gy[s], xg = a.gx[s];
+        double accd[O];
 #pragma unroll
-        for (int o = 0; o < O; ++o) acc[o] = 0.0;
-        int idx = mod_small(kx0, x, a.px, inv_px);  // (kx x) mod px, stepped below
+        for (int oo = 0; oo < O; ++oo) accd[oo] = 0.0;
+        int idx = mod_small(kx0, xg, a.px, inv_px);  // (kx x) mod px, stepped below
         for (int kxl = 0; kxl < nk; ++kxl) {
-            const int kx = kx0 + kxl;
+            const int kxx = kx0 + kxl;
             const cx<R> w = twx[idx];
-            const double cf = (kx == 0 || 2 * kx == a.px) ? 1.0 : 2.0;
+            const double cf = (kxx == 0 || 2 * kxx == a.px) ? 1.0 : 2.0;
 #pragma unroll
-            for (int o = 0; o < O; ++o) {
-                const cx<R> v = buf[(o * KXC + kxl) * PY + y];
-                acc[o] += cf * (double)(v.x * w.x + v.y * w.y);  // Re(v conj(w))
+            for (int oo = 0; oo < O; ++oo) {
+                const cx<R> v = buf[(oo * KXC + kxl) * PS + pslot(y)];
+                accd[oo] += cf * (double)(v.x * w.x + v.y * w.y);  // Re(v conj(w))
             }
-            idx += x;
+            idx += xg;
             if (idx >= a.px) idx -= a.px;
         }
 #pragma unroll
-        for (int o = 0; o < O; ++o) a.partial[((size_t)g * O + o) * a.m + s] = acc[o];
+        for (int oo = 0; oo < O; ++oo) a.partial[((size_t)g * O + oo) * a.m + s] = accd[oo];
     }
 }
 
@@ -438,6 +504,13 @@ int launch_z(const ApplyArgs &a, hipStream_t st) {
 template <typename R, int KIND>
 struct Launch {
     template <int P> static int fwd(const ApplyArgs &a, hipStream_t st) { return launch_fwd<R, P, KIND>(a, st); }
+    template <int P> static int rows(const ApplyArgs &a, hipStream_t st) {
+        using Cfg = RowCfg<R, P, KIND>;
+        dim3 grid((Terms<KIND>::F * a.nd + Cfg::PPB - 1) / Cfg::PPB);
+        hipLaunchKernelGGL((k_rows_fft<R, P, KIND>), grid, dim3(256), 0, st, a);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
     template <int P> static int inv(const ApplyArgs &a, hipStream_t st) { return launch_inv<R, P, KIND>(a, st); }
     template <int P> static int z(const ApplyArgs &a, hipStream_t st) { return launch_z<R, P, KIND>(a, st); }
     template <int P> static int kxc(int) { return InvCfg<R, P, KIND>::KXC; }
@@ -446,6 +519,7 @@ struct Launch {
     static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
         if (ev) BF_HIP(hipEventRecord(ev[0], st));
         hipLaunchKernelGGL((k_fields<R, KIND>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);
+        if (a.nd > 0) BF_CHECK(dispatch_rows(a, st));
         BF_CHECK(dispatch_fwd(a, st));
         if (ev) BF_HIP(hipEventRecord(ev[1], st));
         BF_CHECK(dispatch_z(a, st));
@@ -460,6 +534,11 @@ struct Launch {
     static int dispatch_fwd(const ApplyArgs &a, hipStream_t st) {
         BF_SIZE_SWITCH(a.py, fwd, a, st);
         set_error("unsupported y length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    static int dispatch_rows(const ApplyArgs &a, hipStream_t st) {
+        BF_SIZE_SWITCH(a.px, rows, a, st);
+        set_error("unsupported x length");
         return BEMFFT_EUNSUPPORTED;
     }
     static int dispatch_inv(const ApplyArgs &a, hipStream_t st) {

@@ -256,71 +256,97 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One Stockham stage on a pencil held in LDS.  'tw' is the LDS table
-// tw[t] = exp(-2 pi i t / P); the inverse direction uses its conjugate.
-// FIRST: inputs outside [lo, hi) are read as zero (zero padding without
-// clearing the buffer).
-template <typename R, int P, int TPP, int RAD, int NS, int DIR, bool FIRST>
-__device__ __forceinline__ void stockham_stage(cx<R> *pen, const cx<R> *tw, int t, int lo, int hi) {
+// LDS slot of pencil element i: one pad slot after every 16 elements keeps
+// the stride-R writes of a radix-R stage off a single bank.
+__host__ __device__ constexpr int pslot(int i) { return i + (i >> 4); }
+// LDS elements reserved per pencil.
+template <int P>
+__host__ __device__ constexpr int pstride() { return P + P / 16 + 1; }
+
+// Register layout of a pencil: lane t (0 <= t < TPP) holds x[t + e TPP],
+// e in [0, E).  With the stage rule above this is exactly what the first
+// stage reads and what the last stage writes, for every radix schedule, so a
+// transform starts and ends in registers and only the exchanges between
+// stages pass through the pencil's LDS slots.
+template <typename R, int P, int TPP, int RAD, int NS, int DIR>
+__device__ __forceinline__ void reg_stage(cx<R> (&x)[P / TPP], cx<R> *pen, const cx<R> *tw, int t) {
     constexpr int E = P / TPP;
     constexpr int NB = E / RAD;
     constexpr int STRIDE = P / RAD;
+    constexpr bool FIRST = (NS == 1);
+    constexpr bool LAST = (NS * RAD == P);
     static_assert(E % RAD == 0, "radix must divide the points per lane");
     cx<R> v[NB][RAD];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        int j = t + b * TPP;
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int s = 0; s < RAD; ++s) {
-            const int idx = j + s * STRIDE;
-            if constexpr (FIRST) {
-                v[b][s] = (idx >= lo && idx < hi) ? pen[idx] : cx<R>{R(0), R(0)};
-            } else {
-                v[b][s] = pen[idx];
-            }
+            if constexpr (FIRST) v[b][s] = x[b + s * NB];
+            else v[b][s] = pen[pslot(t + b * TPP + s * STRIDE)];
         }
-    }
-    wave_lds_sync();
+    if constexpr (!FIRST) wave_lds_sync();  // all reads of this stage precede its writes
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        int j = t + b * TPP;
-        int k = j % NS;
+        const int j = t + b * TPP;
+        const int k = j % NS;
         if constexpr (NS > 1) {
             constexpr int TWSTEP = P / (NS * RAD);
 #pragma unroll
             for (int s = 1; s < RAD; ++s) {
-                cx<R> w = tw[s * k * TWSTEP];
+                const cx<R> w = tw[s * k * TWSTEP];
                 v[b][s] = (DIR < 0) ? cmul(v[b][s], w) : cmulc(v[b][s], w);
             }
         }
         DFT<RAD, DIR, R>::run(v[b]);
-        int base = (j / NS) * NS * RAD + k;
+        if constexpr (LAST) {
 #pragma unroll
-        for (int s = 0; s < RAD; ++s) pen[base + s * NS] = v[b][s];
+            for (int s = 0; s < RAD; ++s) x[b + s * NB] = v[b][s];
+        } else {
+            const int base = (j / NS) * NS * RAD + k;
+#pragma unroll
+            for (int s = 0; s < RAD; ++s) pen[pslot(base + s * NS)] = v[b][s];
+        }
     }
-    wave_lds_sync();
+    if constexpr (!LAST) wave_lds_sync();  // writes visible to the next stage
 }
 
 template <typename R, int P, int TPP, int DIR, int NS>
-__device__ __forceinline__ void run_stages(cx<R> *, const cx<R> *, int, int, int, Radices<>) {}
+__device__ __forceinline__ void reg_stages(cx<R> (&)[P / TPP], cx<R> *, const cx<R> *, int, Radices<>) {}
 
 template <typename R, int P, int TPP, int DIR, int NS, int RAD, int... REST>
-__device__ __forceinline__ void run_stages(cx<R> *pen, const cx<R> *tw, int t, int lo, int hi,
+__device__ __forceinline__ void reg_stages(cx<R> (&x)[P / TPP], cx<R> *pen, const cx<R> *tw, int t,
                                            Radices<RAD, REST...>) {
-    stockham_stage<R, P, TPP, RAD, NS, DIR, NS == 1>(pen, tw, t, lo, hi);
-    run_stages<R, P, TPP, DIR, NS * RAD>(pen, tw, t, lo, hi, Radices<REST...>{});
+    reg_stage<R, P, TPP, RAD, NS, DIR>(x, pen, tw, t);
+    reg_stages<R, P, TPP, DIR, NS * RAD>(x, pen, tw, t, Radices<REST...>{});
 }
 
-// Full in-place FFT of one pencil of P points in LDS, unscaled.
-// DIR = -1 forward, +1 inverse.  t in [0, TPP) is the lane's rank in the
-// pencil.  Inputs outside [lo, hi) are taken as zero.  Synchronises only the
-// pencil's own wavefront: the caller puts block barriers around it where
-// other waves wrote or will overwrite the pencil.
+// In-register FFT of one pencil (unscaled; DIR = -1 forward, +1 inverse).
+// x: the lane's E = P/TPP points in the layout above, replaced by the
+// transform in the same layout.  pen: the pencil's pstride<P>() LDS slots
+// (scratch).  tw: LDS table tw[i] = exp(-2 pi i i / P).  Synchronises only
+// the pencil's wavefront.
 template <typename R, int P, int DIR>
-__device__ __forceinline__ void pencil_fft(cx<R> *pen, const cx<R> *tw, int t, int lo = 0, int hi = P) {
+__device__ __forceinline__ void fft_regs(cx<R> (&x)[P / PencilShape<P>::TPP], cx<R> *pen, const cx<R> *tw, int t) {
     using S = PencilShape<P>;
     static_assert(64 % S::TPP == 0, "a pencil must not straddle wavefronts");
-    run_stages<R, P, S::TPP, DIR, 1>(pen, tw, t, lo, hi, typename S::rad{});
+    wave_lds_sync();  // earlier users of the pencil's slots are done
+    reg_stages<R, P, S::TPP, DIR, 1>(x, pen, tw, t, typename S::rad{});
+}
+
+// FFT of a pencil held in LDS slots (pslot layout), in place.
+template <typename R, int P, int DIR>
+__device__ __forceinline__ void pencil_fft(cx<R> *pen, const cx<R> *tw, int t) {
+    using S = PencilShape<P>;
+    constexpr int E = P / S::TPP;
+    cx<R> x[E];
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = pen[pslot(t + e * S::TPP)];
+    fft_regs<R, P, DIR>(x, pen, tw, t);
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) pen[pslot(t + e * S::TPP)] = x[e];
+    wave_lds_sync();
 }
 
 }  // namespace bemfft

@@ -88,7 +88,7 @@ template <int P>
 constexpr int axis_batch() {
     int b = 16;
     if (256 / PencilShape<P>::TPP < b) b = 256 / PencilShape<P>::TPP;
-    int lds = (64 * 1024 - P * 16) / (P * 16);
+    int lds = (64 * 1024 - P * 16) / (pstride<P>() * 16);
     if (lds < b) b = lds;
     return b < 1 ? 1 : b;
 }
@@ -101,7 +101,8 @@ __global__ void k_fft_axis(cx<double> *data, int axis, int64_t px, int64_t py, i
     using S = PencilShape<P>;
     constexpr int B = axis_batch<P>();
     constexpr int NT = B * S::TPP;
-    __shared__ cx<double> buf[B * P];
+    constexpr int PS = pstride<P>();
+    __shared__ cx<double> buf[B * PS];
     __shared__ cx<double> tw[P];
     const int tid = threadIdx.x;
     for (int i = tid; i < P; i += NT) {
@@ -122,16 +123,16 @@ __global__ void k_fft_axis(cx<double> *data, int axis, int64_t px, int64_t py, i
         int b, e;
         if (axis == 0) { b = i / P; e = i % P; } else { e = i / B; b = i % B; }
         int64_t pid = pid0 + b;
-        buf[b * P + e] = (pid < npen) ? data[base_of(pid) + e * stride] : cx<double>{0.0, 0.0};
+        buf[b * PS + pslot(e)] = (pid < npen) ? data[base_of(pid) + e * stride] : cx<double>{0.0, 0.0};
     }
     __syncthreads();
-    pencil_fft<double, P, DIR>(buf + (tid / S::TPP) * P, tw, tid % S::TPP);
+    pencil_fft<double, P, DIR>(buf + (tid / S::TPP) * PS, tw, tid % S::TPP);
     __syncthreads();
     for (int i = tid; i < B * P; i += NT) {
         int b, e;
         if (axis == 0) { b = i / P; e = i % P; } else { e = i / B; b = i % B; }
         int64_t pid = pid0 + b;
-        if (pid < npen) data[base_of(pid) + e * stride] = buf[b * P + e];
+        if (pid < npen) data[base_of(pid) + e * stride] = buf[b * PS + pslot(e)];
     }
 }
 

@@ -128,6 +128,16 @@ def test_laplace3d_cube_parity_all_cmodes(dev):
             assert err < TOL[prec]
 
 
+def test_laplace3d_cube_dense_face_planes(dev):
+    """Rows of 30 nodes on the two z-faces take the row-FFT path."""
+    g = I.cube3d(48, 30).permuted(3)
+    for prec in (B.FP64, B.FP32):
+        err, _ = _parity(dev, g, B.LAPLACE3D, prec)
+        assert err < TOL[prec], (prec, err)
+    err, _ = _parity(dev, I.cube3d(32, 30), B.NAVIER3D, B.FP64)
+    assert err < 1e-12
+
+
 def test_laplace3d_ragged_grid(dev):
     """Unequal axes (n = 40 x 24 x 20, pads 96 x 64 x 64) and a shape that
     touches only a few planes and rows: most rows are empty."""
