@@ -138,7 +138,7 @@ def main():
     u = torch.tensor(un, device=dev)
     r = torch.empty_like(u)
 
-    plan = B.Plan(cube, B.LAPLACE3D, precision=B.FP32)
+    plan = B.Plan(cube, B.LAPLACE3D, precision=B.FP32, keep_fp64=True, autotune=1)
     info = plan.info()
     dt = timed_applies(plan, q, u, r, args.steps, args.warmup)
     value = args.steps / dt
@@ -163,7 +163,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "nodes": cube.m, "grid": 128,
-                   "pad": 256, "edge_points": 100, "occupied_planes": info["z_count"]},
+                   "pad": 256, "edge_points": 100, "occupied_planes": info["z_count"],
+                   "z_schedule": info["zsched"], "autotune_us": info["tune_us"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": stages[dom]["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": stages[dom]["gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(workload, dom)},
@@ -183,7 +184,7 @@ def main():
         qsd = torch.tensor(qs + ns[0], device=dev)
         usd = torch.tensor(us + ns[1], device=dev)
         rs = torch.empty_like(usd)
-        psph = B.Plan(sph, B.LAPLACE3D, precision=B.FP32)
+        psph = B.Plan(sph, B.LAPLACE3D, precision=B.FP32, keep_fp64=True)
         dts = timed_applies(psph, qsd, usd, rs, args.steps, 5)
         extra["sphere_nodes"] = sph.m
         extra["sphere_fp32_matvec_s"] = args.steps / dts
@@ -198,14 +199,17 @@ def main():
             bct = torch.tensor(bc, device=dev)
             if pl64 is None:
                 pl64 = B.Plan(g, B.LAPLACE3D, precision=B.FP64)
-            for tag, pl in (("fp64", pl64), ("fp32", pl32)):
-                pl.solve(bct, known, tol=1e-6)  # warm (workspace allocation)
+            for tag, pl, kw in (("fp64", pl64, {}), ("fp32", pl32, {}),
+                                ("fp32_refined_fp64", pl32, {"refine": 1, "inner_tol": 1e-4})):
+                pl.solve(bct, known, tol=1e-6, **kw)  # warm (workspace allocation)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                x, si = pl.solve(bct, known, tol=1e-6)
+                x, si = pl.solve(bct, known, tol=1e-6, **kw)
                 torch.cuda.synchronize()
                 solves[f"{name}_{tag}"] = {"seconds": time.perf_counter() - t0, "iters": si["iters"],
-                                           "true_relres": si["true_relres"], "status": si["status"]}
+                                           "outer": si["outer"], "true_relres": si["true_relres"],
+                                           "residual_precision": "fp64" if tag != "fp32" else "fp32",
+                                           "status": si["status"]}
         extra["time_to_solve_1e-6"] = solves
         extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
         out["extra"] = extra

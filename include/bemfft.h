@@ -87,6 +87,15 @@ typedef struct {
     const double *c_user;       /* host; m values (Laplace) or m*9 row-major
                                    3x3 blocks (Navier); read if C_USER         */
     void *stream;               /* stream used by plan_create's device work   */
+    int keep_fp64;              /* 1: also keep the FP64 operator of this plan
+                                   (needed by FP64-refined solves of a lower-
+                                   precision plan); default 0                */
+    int autotune;               /* radix schedule of the z transform: 0 the
+                                   default one, 1 time both compiled
+                                   schedules on this plan and keep the faster
+                                   (cached per kernel/precision/padded size
+                                   in the file named by BEMFFT_TUNE_CACHE, if
+                                   set), 2 the alternative one              */
 } bemfft_plan_opts;
 
 /*
@@ -138,14 +147,23 @@ typedef struct {
     int maxit;      /* total iterations (default 1000)                        */
     int precond;    /* 0 none, 1 Jacobi (default 1)                           */
     int use_x0;     /* 1: 'unknown' holds the initial guess on entry          */
+    int refine;     /* 1: iterative refinement -- residuals r = b - A x with
+                       the plan's FP64 operator (plan made with keep_fp64),
+                       corrections from GMRES with the plan's working
+                       precision; 0: plain GMRES in the working precision   */
+    double inner_tol; /* refine: relative tolerance of each inner solve
+                         (default 1e-4)                                     */
+    int max_outer;  /* refine: maximum refinement steps (default 20)          */
 } bemfft_solve_opts;
 
 typedef struct {
-    int iters;          /* GMRES iterations (operator applications)           */
+    int iters;          /* GMRES iterations (working-precision applications)  */
     int restarts;
     double true_relres; /* ||b - A x|| / ||b|| recomputed with a fresh apply  */
     int status;         /* same as the return value                          */
     double seconds;     /* wall time of the call                              */
+    int outer;          /* refinement steps (0 without refine)                */
+    int applies64;      /* FP64 applications made by the refinement            */
 } bemfft_solve_info;
 
 /*
@@ -157,9 +175,13 @@ typedef struct {
  *            u where bc = 1); on entry the initial guess if use_x0.
  * Unknowns x satisfy A x = b with A x = apply(x in the unknown slots) and
  * b = -apply(known values).  Arnoldi, Givens rotations and the true residual
- * are FP64.  Returns 0, ENOCONV (maxit reached; x and info still written),
- * EBREAKDOWN (non-finite values), EINVAL, EDEVICE.  Synchronises 'stream'
- * once per iteration (the convergence scalar crosses to the host).
+ * are FP64.  With opts->refine, b and every residual b - A x use the FP64
+ * operator while the corrections come from GMRES on the working precision
+ * (iterative refinement); the returned true_relres is then the FP64 one.
+ * Returns 0, ENOCONV (maxit reached; x and info still written), EBREAKDOWN
+ * (non-finite values), EINVAL (also: refine on a plan without the FP64
+ * operator), EDEVICE.  Synchronises 'stream' once per iteration (the
+ * convergence scalar crosses to the host).
  */
 int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
                  const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
@@ -175,6 +197,8 @@ typedef struct {
     double spectrum_parity_residual; /* max discarded (imag or real) part of
                                         the kernel spectra / max |spectrum|     */
     double plan_seconds;
+    int zsched;                  /* radix schedule in use for the z transform */
+    double tune_us[2];           /* autotune: mean apply time per schedule, us */
 } bemfft_plan_info;
 
 int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info);

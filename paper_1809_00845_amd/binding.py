@@ -28,17 +28,20 @@ class bemfft_grid(ctypes.Structure):
 
 class bemfft_plan_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("c_mode", ctypes.c_int),
-                ("c_user", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p)]
+                ("c_user", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
+                ("keep_fp64", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class bemfft_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("precond", ctypes.c_int), ("use_x0", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("use_x0", ctypes.c_int), ("refine", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
 
 
 class bemfft_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("true_relres", ctypes.c_double),
-                ("status", ctypes.c_int), ("seconds", ctypes.c_double)]
+                ("status", ctypes.c_int), ("seconds", ctypes.c_double), ("outer", ctypes.c_int),
+                ("applies64", ctypes.c_int)]
 
 
 class bemfft_plan_info(ctypes.Structure):
@@ -48,7 +51,7 @@ class bemfft_plan_info(ctypes.Structure):
                 ("z_count", ctypes.c_int64), ("nfields", ctypes.c_int64), ("nspectra", ctypes.c_int64),
                 ("noutputs", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("spectra_bytes", ctypes.c_int64), ("spectrum_parity_residual", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("zsched", ctypes.c_int), ("tune_us", ctypes.c_double * 2)]
 
 
 EXPORTS = [
@@ -130,7 +133,7 @@ def supported_sizes():
 
 
 def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.0, origin=(0.0, 0.0, 0.0),
-                       pad=(0, 0, 0), precision=FP64, c_mode=C_IMPLICIT, c_user=None, stream=None):
+                       pad=(0, 0, 0), precision=FP64, c_mode=C_IMPLICIT, c_user=None, stream=None, keep_fp64=False, autotune=0):
     """Returns an opaque plan handle (ctypes.c_void_p)."""
     L = load()
     g = bemfft_grid()
@@ -154,6 +157,8 @@ def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.
         c_user = np.ascontiguousarray(c_user, dtype=np.float64)
         opts.c_user = c_user.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     opts.stream = _stream_ptr(stream) if stream is not None else None
+    opts.keep_fp64 = 1 if keep_fp64 else 0
+    opts.autotune = int(autotune)
     h_ = ctypes.c_void_p()
     st = L.bemfft_plan_create(ctypes.byref(h_), ctypes.byref(g), m,
                               nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -176,14 +181,14 @@ def bemfft_apply_profile(plan, q, u, r, reps=10, stream=None):
 
 
 def bemfft_solve(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, precond=1, use_x0=0,
-                 stream=None):
-    o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0)
+                 refine=0, inner_tol=1e-4, max_outer=20, stream=None):
+    o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0, refine, inner_tol, max_outer)
     info = bemfft_solve_info()
     st = load().bemfft_solve(plan, _ptr(bc), _ptr(known), _ptr(unknown), ctypes.byref(o), ctypes.byref(info),
                              _stream_ptr(stream))
     _check(st, "bemfft_solve")
     return {"status": st, "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
-            "seconds": info.seconds}
+            "seconds": info.seconds, "outer": info.outer, "applies64": info.applies64}
 
 
 def bemfft_plan_get_info(plan):
@@ -218,13 +223,14 @@ class Plan:
     normals/weights attributes."""
 
     def __init__(self, geom, kernel, precision=FP64, c_mode=C_IMPLICIT, c_user=None, nu=0.3, mu=1.0,
-                 pad=(0, 0, 0), stream=None):
+                 pad=(0, 0, 0), stream=None, keep_fp64=False, autotune=0):
         self.kernel = kernel
         self.ncomp = 3 if kernel == NAVIER3D else 1
         self.m = int(np.asarray(geom.weights).shape[0])
         self.handle = bemfft_plan_create(geom.dim, geom.n, geom.h, geom.nodes, geom.normals, geom.weights,
                                          kernel, nu, mu, origin=geom.origin, pad=pad, precision=precision,
-                                         c_mode=c_mode, c_user=c_user, stream=stream)
+                                         c_mode=c_mode, c_user=c_user, stream=stream, keep_fp64=keep_fp64,
+                                         autotune=autotune)
 
     def apply(self, q, u, r=None, stream=None):
         import torch

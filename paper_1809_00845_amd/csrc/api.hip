@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -186,6 +188,7 @@ int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double 
     a.dense_rows = p->d_dense_rows;
     a.nd = (int)p->nd;
     a.node_splits = (int)std::max<int64_t>(1, (p->max_plane_nodes + kGatherChunk - 1) / kGatherChunk);
+    a.zsched = p->zsched;
     if (p->kernel == 0) return apply_kind<0>(e.precision, a, st, ev);
     if (p->kernel == 1) return apply_kind<1>(e.precision, a, st, ev);
     return apply_kind<2>(e.precision, a, st, ev);
@@ -199,6 +202,7 @@ namespace {
 
 void destroy_plan_state(bemfft_plan *p) {
     free_engine(&p->eng);
+    free_engine(&p->eng64);
     dev_free(p->d_gx);
     dev_free(p->d_gy);
     dev_free(p->d_gz);
@@ -255,6 +259,8 @@ int implicit_free_term(bemfft_plan *p, const Engine &e64, hipStream_t st, std::v
     if (status == BEMFFT_EDEVICE) set_error("implicit free term: HIP failure");
     return status;
 }
+
+int autotune_zsched(bemfft_plan *p, hipStream_t st);
 
 int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const double *nodes,
                      const double *normals, const double *weights, int kernel, double nu, double mu,
@@ -424,6 +430,7 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     }
     if (prec == BEMFFT_FP64) {
         p->eng = e64;
+        p->has64 = true;
     } else {
         Engine e32;
         e32.precision = BEMFFT_FP32;
@@ -441,12 +448,99 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
                 set_error("spectrum conversion failed");
             }
         }
-        free_engine(&e64);
-        if (status) { free_engine(&e32); return status; }
+        if (status == 0 && opts && opts->keep_fp64) {
+            p->eng64 = e64;  // the refinement's FP64 operator
+            p->has64 = true;
+        } else {
+            free_engine(&e64);
+        }
+        if (status) { free_engine(&e32); free_engine(&p->eng64); p->has64 = false; return status; }
         p->eng = e32;
     }
     if (hipStreamSynchronize(st) != hipSuccess) { set_error("plan: stream sync failed"); return BEMFFT_EDEVICE; }
+    const int tune = opts ? opts->autotune : 0;
+    if (tune == 2) p->zsched = 1;
+    else if (tune == 1 && p->dim == 3) BF_CHECK(autotune_zsched(p, st));
     p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return 0;
+}
+
+std::string tune_key(const bemfft_plan *p) {
+    return std::to_string(p->kernel) + ":" + std::to_string(p->eng.precision) + ":" + std::to_string(p->P[0]) + "x" +
+           std::to_string(p->P[1]) + "x" + std::to_string(p->P[2]);
+}
+
+int tune_cache_lookup(const std::string &key) {
+    const char *path = std::getenv("BEMFFT_TUNE_CACHE");
+    if (!path || !*path) return -1;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char k[128];
+    int v = -1, found = -1;
+    while (std::fscanf(f, "%127s %d", k, &v) == 2)
+        if (key == k) found = v;
+    std::fclose(f);
+    return (found == 0 || found == 1) ? found : -1;
+}
+
+void tune_cache_store(const std::string &key, int v) {
+    const char *path = std::getenv("BEMFFT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), v);
+    std::fclose(f);
+}
+
+// Time the working-precision apply with each compiled z schedule and keep
+// the faster one.
+int autotune_zsched(bemfft_plan *p, hipStream_t st) {
+    const std::string key = tune_key(p);
+    const int cached = tune_cache_lookup(key);
+    if (cached >= 0) {
+        p->zsched = cached;
+        return 0;
+    }
+    const size_t bytes = (size_t)p->ncomp * p->m * sizeof(double);
+    double *q = nullptr, *u = nullptr, *r = nullptr;
+    hipEvent_t e0, e1;
+    if (hipMalloc(&q, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess || hipMalloc(&r, bytes) != hipSuccess) {
+        dev_free(q);
+        dev_free(u);
+        dev_free(r);
+        set_error("autotune: allocation failed");
+        return BEMFFT_ENOMEM;
+    }
+    std::vector<double> ones((size_t)p->ncomp * p->m, 1.0);
+    int status = 0;
+    if (hipMemcpy(q, ones.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(u, ones.data(), bytes, hipMemcpyHostToDevice) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        status = BEMFFT_EDEVICE;
+    const int reps = 20;
+    for (int sched = 0; sched < 2 && status == 0; ++sched) {
+        p->zsched = sched;
+        for (int i = 0; i < 3 && status == 0; ++i) status = launch_apply(p, p->eng, q, u, r, st);
+        if (status) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        for (int i = 0; i < reps && status == 0; ++i) status = launch_apply(p, p->eng, q, u, r, st);
+        float ms = 0.f;
+        if (status == 0 && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            status = BEMFFT_EDEVICE;
+        p->tune_us[sched] = 1e3 * ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_free(q);
+    dev_free(u);
+    dev_free(r);
+    if (status) {
+        if (status == BEMFFT_EDEVICE) set_error("autotune: HIP failure");
+        return status;
+    }
+    p->zsched = p->tune_us[1] < p->tune_us[0] ? 1 : 0;
+    tune_cache_store(key, p->zsched);
     return 0;
 }
 
@@ -538,10 +632,13 @@ int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {
     info->nfields = p->F;
     info->nspectra = p->K;
     info->noutputs = p->O;
-    info->workspace_bytes = (int64_t)p->eng.bytes;
+    info->workspace_bytes = (int64_t)(p->eng.bytes + p->eng64.bytes);
     info->spectra_bytes = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2] * (int64_t)p->eng.creal;
     info->spectrum_parity_residual = p->parity_resid;
     info->plan_seconds = p->plan_seconds;
+    info->zsched = p->zsched;
+    info->tune_us[0] = p->tune_us[0];
+    info->tune_us[1] = p->tune_us[1];
     return 0;
 }
 

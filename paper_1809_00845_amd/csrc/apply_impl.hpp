@@ -38,6 +38,7 @@ struct ApplyArgs {
     int m;
     int G;
     int node_splits;  // node chunks per plane in the gather
+    int zsched;       // radix schedule of the z pass (0 or 1)
     const int *gx, *gy, *rowptr, *perm;
     const double *w, *nrm, *C, *SC;
     const double *q, *u;
@@ -241,9 +242,10 @@ __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs 
 // its first FFT stage needs straight into registers, multiplies the
 // transformed values in registers, and stores the inverse transform's rows
 // from registers: LDS only carries the exchange between FFT stages.
-template <typename R, int PZ, int KIND>
+template <typename R, typename SH, int KIND>
 struct ZCfg {
-    static constexpr int TPP = PencilShape<PZ>::TPP;
+    static constexpr int PZ = SH::P;
+    static constexpr int TPP = SH::TPP;
     static constexpr int PPW = 64 / TPP;
     static constexpr int CB = (int)sizeof(cx<R>);
     static constexpr int PS = pstride<PZ>();
@@ -276,9 +278,10 @@ __device__ __forceinline__ void mac(cx<R> &acc, cx<R> v, R s, bool imag) {
     }
 }
 
-template <typename R, int PZ, int KIND>
-__global__ __launch_bounds__((ZCfg<R, PZ, KIND>::NT)) void k_zpass(ApplyArgs a) {
-    using Cfg = ZCfg<R, PZ, KIND>;
+template <typename R, typename SH, int KIND>
+__global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a) {
+    using Cfg = ZCfg<R, SH, KIND>;
+    constexpr int PZ = SH::P;
     using T = Terms<KIND>;
     constexpr int PPW = Cfg::PPW, TY = Cfg::TY, NT = Cfg::NT, TPP = Cfg::TPP, E = Cfg::E, PS = Cfg::PS;
     constexpr int F = T::F, O = T::O;
@@ -310,7 +313,7 @@ __global__ __launch_bounds__((ZCfg<R, PZ, KIND>::NT)) void k_zpass(ApplyArgs a) 
             const int zz = t + e * TPP - a.z0;  // occupied plane index; others are zero
             x[e] = (live && zz >= 0 && zz < a.nzo) ? Yf[(size_t)zz * a.py + ky] : cx<R>{R(0), R(0)};
         }
-        fft_regs<R, PZ, -1>(x, pb, tw, t);
+        fft_regs_s<R, SH, -1>(x, pb, tw, t);
         if (live) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -328,7 +331,7 @@ __global__ __launch_bounds__((ZCfg<R, PZ, KIND>::NT)) void k_zpass(ApplyArgs a) 
 
 #pragma unroll
     for (int o = 0; o < O; ++o) {
-        fft_regs<R, PZ, 1>(acc[o], pb, tw, t);
+        fft_regs_s<R, SH, 1>(acc[o], pb, tw, t);
         if (live) {
             cx<R> *Zo = static_cast<cx<R> *>(a.Z) + (size_t)(o * a.hx + kx) * a.nzo * a.py;
 #pragma unroll
@@ -473,15 +476,16 @@ int launch_inv(const ApplyArgs &a, hipStream_t st) {
     BF_HIP(hipGetLastError());
     return 0;
 }
-template <typename R, int PZ, int KIND>
+template <typename R, int PZ, int KIND, int SCHED>
 int launch_z(const ApplyArgs &a, hipStream_t st) {
     if constexpr (PZ == 1) {
         dim3 grid(a.hx, (a.py + 255) / 256);
         hipLaunchKernelGGL((k_mac2d<R, KIND>), grid, dim3(256), 0, st, a);
     } else {
-        using Cfg = ZCfg<R, PZ, KIND>;
+        using SH = Sched<PZ, SCHED>;
+        using Cfg = ZCfg<R, SH, KIND>;
         dim3 grid(a.hx, (a.py + Cfg::TY - 1) / Cfg::TY);
-        hipLaunchKernelGGL((k_zpass<R, PZ, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+        hipLaunchKernelGGL((k_zpass<R, SH, KIND>), grid, dim3(Cfg::NT), 0, st, a);
     }
     BF_HIP(hipGetLastError());
     return 0;
@@ -512,7 +516,9 @@ struct Launch {
         return 0;
     }
     template <int P> static int inv(const ApplyArgs &a, hipStream_t st) { return launch_inv<R, P, KIND>(a, st); }
-    template <int P> static int z(const ApplyArgs &a, hipStream_t st) { return launch_z<R, P, KIND>(a, st); }
+    template <int P> static int z(const ApplyArgs &a, hipStream_t st) {
+        return a.zsched ? launch_z<R, P, KIND, 1>(a, st) : launch_z<R, P, KIND, 0>(a, st);
+    }
     template <int P> static int kxc(int) { return InvCfg<R, P, KIND>::KXC; }
 
     // ev (optional): five events recorded around the four stages.
@@ -548,7 +554,7 @@ struct Launch {
     }
     static int dispatch_z(const ApplyArgs &a, hipStream_t st) {
         if constexpr (KIND == 0) {
-            if (a.pz == 1) return z<1>(a, st);
+            if (a.pz == 1) return launch_z<R, 1, KIND, 0>(a, st);
             set_error("2D plans need pz == 1");
             return BEMFFT_EUNSUPPORTED;
         } else {

@@ -233,18 +233,41 @@ template <int DIR, typename R> struct DFT<20, DIR, R> : DFTSplit<20, 4, 5, DIR, 
 template <int... Rs>
 struct Radices {};
 
+// A radix schedule: P points per pencil, TPP lanes per pencil, radices Rs.
+template <int P_, int TPP_, int... Rs>
+struct FFTShape {
+    static constexpr int P = P_;
+    static constexpr int TPP = TPP_;
+    static constexpr int E = P_ / TPP_;
+    using rad = Radices<Rs...>;
+};
+
+// Two compiled schedules per length (S = 0 default, S = 1 alternative); the
+// plan's autotuner picks one for the z pass by timing both.
+template <int P, int S>
+struct Sched;
+template <> struct Sched<1, 0> : FFTShape<1, 1> {};
+template <> struct Sched<32, 0> : FFTShape<32, 4, 4, 8> {};
+template <> struct Sched<32, 1> : FFTShape<32, 4, 8, 4> {};
+template <> struct Sched<64, 0> : FFTShape<64, 8, 8, 8> {};
+template <> struct Sched<64, 1> : FFTShape<64, 4, 16, 4> {};
+template <> struct Sched<96, 0> : FFTShape<96, 8, 4, 4, 6> {};
+template <> struct Sched<96, 1> : FFTShape<96, 8, 6, 4, 4> {};
+template <> struct Sched<128, 0> : FFTShape<128, 8, 16, 8> {};
+template <> struct Sched<128, 1> : FFTShape<128, 16, 8, 4, 4> {};
+template <> struct Sched<192, 0> : FFTShape<192, 16, 4, 4, 12> {};
+template <> struct Sched<192, 1> : FFTShape<192, 16, 12, 4, 4> {};
+template <> struct Sched<256, 0> : FFTShape<256, 16, 16, 16> {};
+template <> struct Sched<256, 1> : FFTShape<256, 32, 8, 8, 4> {};
+template <> struct Sched<320, 0> : FFTShape<320, 16, 4, 4, 20> {};
+template <> struct Sched<320, 1> : FFTShape<320, 16, 20, 4, 4> {};
+template <> struct Sched<384, 0> : FFTShape<384, 16, 8, 6, 8> {};
+template <> struct Sched<384, 1> : FFTShape<384, 16, 6, 8, 8> {};
+template <> struct Sched<512, 0> : FFTShape<512, 32, 8, 8, 8> {};
+template <> struct Sched<512, 1> : FFTShape<512, 32, 16, 4, 8> {};
+
 template <int P>
-struct PencilShape;
-template <> struct PencilShape<1>   { static constexpr int TPP = 1;  using rad = Radices<>; };
-template <> struct PencilShape<32>  { static constexpr int TPP = 4;  using rad = Radices<4, 8>; };
-template <> struct PencilShape<64>  { static constexpr int TPP = 8;  using rad = Radices<8, 8>; };
-template <> struct PencilShape<96>  { static constexpr int TPP = 8;  using rad = Radices<4, 4, 6>; };
-template <> struct PencilShape<128> { static constexpr int TPP = 8;  using rad = Radices<16, 8>; };
-template <> struct PencilShape<192> { static constexpr int TPP = 16; using rad = Radices<4, 4, 12>; };
-template <> struct PencilShape<256> { static constexpr int TPP = 16; using rad = Radices<16, 16>; };
-template <> struct PencilShape<320> { static constexpr int TPP = 16; using rad = Radices<4, 4, 20>; };
-template <> struct PencilShape<384> { static constexpr int TPP = 16; using rad = Radices<8, 6, 8>; };
-template <> struct PencilShape<512> { static constexpr int TPP = 32; using rad = Radices<8, 8, 8>; };
+using PencilShape = Sched<P, 0>;
 
 // Lanes of one pencil always sit in one wavefront, so the exchanges inside a
 // transform only need the wave's LDS accesses to stay in program order (LDS
@@ -320,17 +343,21 @@ __device__ __forceinline__ void reg_stages(cx<R> (&x)[P / TPP], cx<R> *pen, cons
     reg_stages<R, P, TPP, DIR, NS * RAD>(x, pen, tw, t, Radices<REST...>{});
 }
 
-// In-register FFT of one pencil (unscaled; DIR = -1 forward, +1 inverse).
-// x: the lane's E = P/TPP points in the layout above, replaced by the
-// transform in the same layout.  pen: the pencil's pstride<P>() LDS slots
-// (scratch).  tw: LDS table tw[i] = exp(-2 pi i i / P).  Synchronises only
-// the pencil's wavefront.
+// In-register FFT of one pencil (unscaled; DIR = -1 forward, +1 inverse)
+// with schedule SH.  x: the lane's E = P/TPP points in the layout above,
+// replaced by the transform in the same layout.  pen: the pencil's
+// pstride<P>() LDS slots (scratch).  tw: LDS table tw[i] = exp(-2 pi i i / P).
+// Synchronises only the pencil's wavefront.
+template <typename R, typename SH, int DIR>
+__device__ __forceinline__ void fft_regs_s(cx<R> (&x)[SH::E], cx<R> *pen, const cx<R> *tw, int t) {
+    static_assert(64 % SH::TPP == 0, "a pencil must not straddle wavefronts");
+    wave_lds_sync();  // earlier users of the pencil's slots are done
+    reg_stages<R, SH::P, SH::TPP, DIR, 1>(x, pen, tw, t, typename SH::rad{});
+}
+
 template <typename R, int P, int DIR>
 __device__ __forceinline__ void fft_regs(cx<R> (&x)[P / PencilShape<P>::TPP], cx<R> *pen, const cx<R> *tw, int t) {
-    using S = PencilShape<P>;
-    static_assert(64 % S::TPP == 0, "a pencil must not straddle wavefronts");
-    wave_lds_sync();  // earlier users of the pencil's slots are done
-    reg_stages<R, P, S::TPP, DIR, 1>(x, pen, tw, t, typename S::rad{});
+    fft_regs_s<R, PencilShape<P>, DIR>(x, pen, tw, t);
 }
 
 // FFT of a pencil held in LDS slots (pslot layout), in place.

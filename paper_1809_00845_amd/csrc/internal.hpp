@@ -88,9 +88,13 @@ struct bemfft_plan {
     double *d_C = nullptr;     // [m][O][O] free term
     double *d_SC = nullptr;    // [m][O][O] self-term correction (exact - grid)
     bemfft::Engine eng;        // working precision
+    bemfft::Engine eng64;      // FP64 operator kept for refinement (if not the working one)
+    bool has64 = false;        // an FP64 operator is available (eng or eng64)
     std::vector<double> h_c;   // c values in caller order (m or 9 m)
     std::vector<double> h_diag_dir, h_diag_neu;  // Jacobi entries per slot
     double parity_resid = 0.0;
+    int zsched = 0;               // radix schedule of the z transform
+    double tune_us[2] = {0, 0};
     double plan_seconds = 0.0;
     // solve workspace, allocated on first use
     double *s_V = nullptr;

@@ -21,7 +21,7 @@
 namespace bemfft {
 namespace {
 
-constexpr int kRedBlocks = 240;
+constexpr int kRedBlocks = 256;
 constexpr int kRedThreads = 256;
 
 // x_in -> (q, u) split by the flags: slot with bc = 0 has u known, so its
@@ -49,27 +49,40 @@ __global__ void k_diag(const uint8_t *bc, const double *ddir, const double *dneu
 }
 
 // partial[blk][j] = sum over this block's rows of V[j][i] w[i], j < nvec.
+// Eight vectors per sweep over the rows; wavefront sums by lane shuffles,
+// then one LDS step across the block's four wavefronts (fixed order: the
+// result is bitwise reproducible).
 __global__ __launch_bounds__(kRedThreads) void k_mdot_partial(const double *V, int64_t ld, int nvec,
                                                               const double *w, int64_t n, double *partial) {
-    __shared__ double sm[kRedThreads];
-    for (int j0 = 0; j0 < nvec; j0 += 4) {
-        double acc[4] = {0, 0, 0, 0};
-        for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
-            double wi = w[i];
+    constexpr int G = 8;
+    constexpr int NW = kRedThreads / 64;
+    __shared__ double sm[NW][G];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    for (int j0 = 0; j0 < nvec; j0 += G) {
+        double acc[G];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < G; ++k) acc[k] = 0.0;
+        for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+            const double wi = w[i];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
                 if (j0 + k < nvec) acc[k] += V[(int64_t)(j0 + k) * ld + i] * wi;
         }
-        for (int k = 0; k < 4 && j0 + k < nvec; ++k) {
-            sm[threadIdx.x] = acc[k];
-            __syncthreads();
-            for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-                if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * nvec + j0 + k] = sm[0];
-            __syncthreads();
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < G; ++k) sm[wave][k] = acc[k];
+        __syncthreads();
+        if (threadIdx.x < G && j0 + threadIdx.x < nvec) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s += sm[q][threadIdx.x];
+            partial[(int64_t)blockIdx.x * nvec + j0 + threadIdx.x] = s;
         }
+        __syncthreads();
     }
 }
 
@@ -81,11 +94,18 @@ __global__ void k_mdot_final(const double *partial, int nblk, int nvec, double *
     out[j] = (sqrt_last && j == nvec - 1) ? sqrt(s) : s;
 }
 
-// w[i] += sign * sum_j V[j][i] h[j]
+// w[i] += sign * sum_j V[j][i] h[j]; eight independent partial sums keep
+// eight loads of V in flight per row.
 __global__ void k_gemv(const double *V, int64_t ld, int nvec, const double *h, double *w, int64_t n, double sign) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int j = 0; j < nvec; ++j) s += V[(int64_t)j * ld + i] * h[j];
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int j = 0;
+        for (; j + 8 <= nvec; j += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        }
+        for (int k = 0; j + k < nvec; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         w[i] += sign * s;
     }
 }
@@ -106,7 +126,7 @@ __global__ void k_mul(double *y, const double *a, int64_t n) {
 int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); }
 
 struct Ws {
-    double *V, *b, *x, *w, *q, *u, *r, *dinv, *red, *hd;
+    double *V, *b, *x, *w, *q, *u, *r, *dinv, *ro, *d, *red, *hd;
     int cap;
 };
 
@@ -123,7 +143,7 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
         p->s_cap = restart + 1;
     }
     if (!p->s_vec) {
-        if (hipMalloc(&p->s_vec, 7 * (size_t)n * sizeof(double)) != hipSuccess ||
+        if (hipMalloc(&p->s_vec, 9 * (size_t)n * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->s_red, (size_t)kRedBlocks * 512 * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->s_hbuf, 2 * 512 * sizeof(double)) != hipSuccess ||
             hipHostMalloc(&p->h_pinned, 2 * 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -140,6 +160,8 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
     ws.u = ws.q + n;
     ws.r = ws.u + n;
     ws.dinv = ws.r + n;
+    ws.ro = ws.dinv + n;
+    ws.d = ws.ro + n;
     ws.red = p->s_red;
     ws.hd = p->s_hbuf;
     return 0;
@@ -154,22 +176,148 @@ int mdot(const double *V, int64_t ld, int nvec, const double *w, int64_t n, doub
     return 0;
 }
 
-// r = A x = apply(x in the unknown slots, scaled by 'scale' if given)
-int apply_unknown(bemfft_plan *p, const uint8_t *bc, const double *x, const double *scale, Ws &ws, double *out,
-                  hipStream_t st) {
+// out = A x = apply(x in the unknown slots, scaled by 'scale' if given)
+int apply_unknown(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double *x, const double *scale, Ws &ws,
+                  double *out, hipStream_t st) {
     const int64_t n = (int64_t)p->ncomp * p->m;
     hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(256), 0, st, bc, x, scale, ws.q, ws.u, n, 1);
     BF_HIP(hipGetLastError());
-    return launch_apply(p, p->eng, ws.q, ws.u, out, st);
+    return launch_apply(p, e, ws.q, ws.u, out, st);
 }
 
-double read_scalar(const double *d, double *pinned, hipStream_t st, int *status) {
-    if (hipMemcpyAsync(pinned, d, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+// ||v||_2 (one host round trip)
+double norm2(const double *v, int64_t n, Ws &ws, double *pinned, hipStream_t st, int *status) {
+    *status = mdot(v, n, 1, v, n, ws.red, ws.hd, 1, st);
+    if (*status) return NAN;
+    if (hipMemcpyAsync(pinned, ws.hd, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         *status = BEMFFT_EDEVICE;
+        set_error("GMRES: device-to-host copy failed");
         return NAN;
     }
     return pinned[0];
+}
+
+// Restarted GMRES with right scaling Dinv on the operator of engine e:
+// solves A x = rhs, x in/out (x_zero: x is zero on entry), relative true
+// residual tolerance tol, at most maxit iterations.  Uses ws.w, ws.r, ws.q,
+// ws.u, ws.V.  Returns the status; iters and the final true relative
+// residual (w.r.t. ||rhs||) through the pointers.
+int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double *rhs, double *x, bool x_zero,
+               double tol, int mcap, int maxit, Ws &ws, double *hp, hipStream_t st, int *iters_out, int *restarts_out,
+               double *relres_out) {
+    const int64_t n = (int64_t)p->ncomp * p->m;
+    int status = 0;
+    const double bnorm = norm2(rhs, n, ws, hp, st, &status);
+    BF_CHECK(status);
+    int iters = 0, cycles = 0;
+    double true_rel = 0.0;
+    std::vector<double> H((size_t)(mcap + 1) * mcap), cs(mcap), sn(mcap), g(mcap + 1), y(mcap);
+    if (!std::isfinite(bnorm)) {
+        set_error("GMRES: right-hand side is not finite");
+        return BEMFFT_EBREAKDOWN;
+    }
+    if (bnorm == 0.0) {
+        BF_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+        *iters_out = 0;
+        *restarts_out = 0;
+        *relres_out = 0.0;
+        return 0;
+    }
+    for (;;) {
+        // r0 = rhs - A x
+        if (x_zero) {
+            BF_HIP(hipMemcpyAsync(ws.w, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        } else {
+            BF_CHECK(apply_unknown(p, e, bc, x, nullptr, ws, ws.w, st));
+            hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.w, rhs, 1.0, -1.0, n);
+        }
+        const double beta = norm2(ws.w, n, ws, hp, st, &status);
+        BF_CHECK(status);
+        true_rel = beta / bnorm;
+        if (!std::isfinite(beta)) {
+            status = BEMFFT_EBREAKDOWN;
+            set_error("GMRES: non-finite residual");
+            break;
+        }
+        if (true_rel <= tol) break;
+        if (iters >= maxit) {
+            status = BEMFFT_ENOCONV;
+            break;
+        }
+        hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(256), 0, st, ws.w, ws.hd, ws.V, n);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool breakdown = false;
+        for (; k < mcap && iters < maxit; ++k) {
+            double *vk = ws.V + (int64_t)k * n;
+            // w = A Dinv v_k
+            BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
+            // classical Gram-Schmidt, twice
+            double *h1 = ws.hd, *h2 = ws.hd + 512;
+            BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h1, 0, st));
+            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h1, ws.w, n, -1.0);
+            BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h2, 0, st));
+            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h2, ws.w, n, -1.0);
+            BF_CHECK(mdot(ws.w, n, 1, ws.w, n, ws.red, h2 + k + 1, 1, st));
+            hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(256), 0, st, ws.w, h2 + k + 1,
+                               ws.V + (int64_t)(k + 1) * n, n);
+            BF_HIP(hipGetLastError());
+            BF_HIP(hipMemcpyAsync(hp, ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
+            BF_HIP(hipStreamSynchronize(st));
+            ++iters;
+            double *col = &H[(size_t)k * (mcap + 1)];
+            for (int i = 0; i <= k; ++i) col[i] = hp[i] + hp[512 + i];
+            col[k + 1] = hp[512 + k + 1];
+            for (int i = 0; i <= k + 1; ++i)
+                if (!std::isfinite(col[i])) breakdown = true;
+            if (breakdown) break;
+            for (int i = 0; i < k; ++i) {
+                double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            double a = col[k], bb = col[k + 1];
+            double rr = std::hypot(a, bb);
+            cs[k] = rr > 0.0 ? a / rr : 1.0;
+            sn[k] = rr > 0.0 ? bb / rr : 0.0;
+            col[k] = rr;
+            col[k + 1] = 0.0;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            const double est = std::fabs(g[k + 1]) / bnorm;
+            if (est <= tol || hp[512 + k + 1] == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        if (breakdown) {
+            status = BEMFFT_EBREAKDOWN;
+            set_error("GMRES: non-finite Hessenberg entry");
+            break;
+        }
+        // y = H^{-1} g (upper triangular, k x k)
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int j = i + 1; j < k; ++j) s -= H[(size_t)j * (mcap + 1) + i] * y[j];
+            double d = H[(size_t)i * (mcap + 1) + i];
+            y[i] = d != 0.0 ? s / d : 0.0;
+        }
+        // x += Dinv V y
+        BF_HIP(hipMemcpyAsync(ws.hd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+        BF_HIP(hipMemsetAsync(ws.r, 0, n * sizeof(double), st));
+        hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k, ws.hd, ws.r, n, 1.0);
+        hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(256), 0, st, ws.r, ws.dinv, n);
+        hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, x, ws.r, 1.0, 1.0, n);
+        BF_HIP(hipGetLastError());
+        x_zero = false;
+        ++cycles;
+    }
+    *iters_out = iters;
+    *restarts_out = cycles > 0 ? cycles - 1 : 0;
+    *relres_out = true_rel;
+    return status;
 }
 
 }  // namespace
@@ -184,14 +332,20 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
         set_error("solve: null argument");
         return BEMFFT_EINVAL;
     }
-    bemfft_solve_opts o{1e-6, 100, 1000, 1, 0};
+    bemfft_solve_opts o{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
     if (opts) o = *opts;
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1) {
         set_error("solve: bad options");
         return BEMFFT_EINVAL;
     }
+    if (o.refine && (!p->has64 || !(o.inner_tol > 0.0) || o.max_outer < 1)) {
+        set_error("solve: refinement needs a plan created with keep_fp64 (or FP64), inner_tol > 0, max_outer >= 1");
+        return BEMFFT_EINVAL;
+    }
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = (int64_t)p->ncomp * p->m;
+    const Engine &e64 = (p->eng.precision == BEMFFT_FP64) ? p->eng : p->eng64;
+    const Engine &eo = o.refine ? e64 : p->eng;  // operator of b and of the true residual
     Ws ws{};
     BF_CHECK(ensure_workspace(p, o.restart, ws));
     double *hp = p->h_pinned;
@@ -200,7 +354,7 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
     hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(256), 0, st, bc, known, (const double *)nullptr, ws.q, ws.u,
                        n, 0);
     BF_HIP(hipGetLastError());
-    BF_CHECK(launch_apply(p, p->eng, ws.q, ws.u, ws.b, st));
+    BF_CHECK(launch_apply(p, eo, ws.q, ws.u, ws.b, st));
     hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.b, ws.b, -1.0, 0.0, n);
     // Jacobi scaling
     {
@@ -212,129 +366,62 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
     }
     if (o.use_x0) BF_HIP(hipMemcpyAsync(ws.x, unknown, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     else BF_HIP(hipMemsetAsync(ws.x, 0, n * sizeof(double), st));
-    BF_CHECK(mdot(ws.b, n, 1, ws.b, n, ws.red, ws.hd, 1, st));
-    const double bnorm = read_scalar(ws.hd, hp, st, &status);
-    BF_CHECK(status);
-    int iters = 0, restarts = 0;
-    double true_rel = 0.0;
-    const int mcap = o.restart;
-    std::vector<double> H((size_t)(mcap + 1) * mcap), cs(mcap), sn(mcap), g(mcap + 1), y(mcap);
-    if (!std::isfinite(bnorm)) {
-        status = BEMFFT_EBREAKDOWN;
-        set_error("right-hand side is not finite");
-    } else if (bnorm == 0.0) {
-        BF_HIP(hipMemsetAsync(ws.x, 0, n * sizeof(double), st));
-        true_rel = 0.0;
+    int iters = 0, restarts = 0, outer = 0, applies64 = 1;
+    double rel = 0.0;
+    if (!o.refine) {
+        status = gmres_core(p, p->eng, bc, ws.b, ws.x, !o.use_x0, o.tol, o.restart, o.maxit, ws, hp, st, &iters,
+                            &restarts, &rel);
     } else {
-        bool done = false;
+        // iterative refinement: r = b - A64 x in FP64, d ~ A^-1 r in the
+        // working precision, x += d
+        int st2 = 0;
+        const double bnorm = norm2(ws.b, n, ws, hp, st, &st2);
+        BF_CHECK(st2);
         bool x_zero = !o.use_x0;
-        while (!done) {
-            // r0 = b - A x
+        for (;;) {
             if (x_zero) {
-                BF_HIP(hipMemcpyAsync(ws.w, ws.b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                BF_HIP(hipMemcpyAsync(ws.ro, ws.b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
             } else {
-                BF_CHECK(apply_unknown(p, bc, ws.x, nullptr, ws, ws.w, st));
-                hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.w, ws.b, 1.0, -1.0, n);
+                BF_CHECK(apply_unknown(p, e64, bc, ws.x, nullptr, ws, ws.ro, st));
+                ++applies64;
+                hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.ro, ws.b, 1.0, -1.0, n);
             }
-            BF_CHECK(mdot(ws.w, n, 1, ws.w, n, ws.red, ws.hd, 1, st));
-            const double beta = read_scalar(ws.hd, hp, st, &status);
-            BF_CHECK(status);
-            true_rel = beta / bnorm;
-            if (!std::isfinite(beta)) {
+            const double rn = norm2(ws.ro, n, ws, hp, st, &st2);
+            BF_CHECK(st2);
+            rel = bnorm > 0.0 ? rn / bnorm : 0.0;
+            if (!std::isfinite(rn)) {
                 status = BEMFFT_EBREAKDOWN;
-                set_error("GMRES: non-finite residual");
+                set_error("refinement: non-finite residual");
                 break;
             }
-            if (true_rel <= o.tol) {
-                status = 0;
-                break;
-            }
-            if (iters >= o.maxit) {
-                status = BEMFFT_ENOCONV;
-                break;
-            }
-            if (restarts > 0 || !x_zero) {
-                // keep going from the current x
-            }
-            hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(256), 0, st, ws.w, ws.hd, ws.V, n);
-            std::fill(g.begin(), g.end(), 0.0);
-            g[0] = beta;
-            int k = 0;
-            bool breakdown = false;
-            for (; k < mcap && iters < o.maxit; ++k) {
-                double *vk = ws.V + (int64_t)k * n;
-                // w = A Dinv v_k
-                BF_CHECK(apply_unknown(p, bc, vk, ws.dinv, ws, ws.w, st));
-                // classical Gram-Schmidt, twice
-                double *h1 = ws.hd, *h2 = ws.hd + 512;
-                BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h1, 0, st));
-                hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h1, ws.w, n, -1.0);
-                BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h2, 0, st));
-                hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h2, ws.w, n, -1.0);
-                BF_CHECK(mdot(ws.w, n, 1, ws.w, n, ws.red, h2 + k + 1, 1, st));
-                hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(256), 0, st, ws.w, h2 + k + 1,
-                                   ws.V + (int64_t)(k + 1) * n, n);
-                BF_HIP(hipGetLastError());
-                BF_HIP(hipMemcpyAsync(hp, ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
-                BF_HIP(hipStreamSynchronize(st));
-                ++iters;
-                double *col = &H[(size_t)k * (mcap + 1)];
-                for (int i = 0; i <= k; ++i) col[i] = hp[i] + hp[512 + i];
-                col[k + 1] = hp[512 + k + 1];
-                for (int i = 0; i <= k + 1; ++i)
-                    if (!std::isfinite(col[i])) breakdown = true;
-                if (breakdown) break;
-                for (int i = 0; i < k; ++i) {
-                    double t = cs[i] * col[i] + sn[i] * col[i + 1];
-                    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-                    col[i] = t;
-                }
-                double a = col[k], bb = col[k + 1];
-                double rr = std::hypot(a, bb);
-                cs[k] = rr > 0.0 ? a / rr : 1.0;
-                sn[k] = rr > 0.0 ? bb / rr : 0.0;
-                col[k] = rr;
-                col[k + 1] = 0.0;
-                g[k + 1] = -sn[k] * g[k];
-                g[k] = cs[k] * g[k];
-                const double est = std::fabs(g[k + 1]) / bnorm;
-                if (est <= o.tol || hp[512 + k + 1] == 0.0) {
-                    ++k;
-                    break;
-                }
-            }
-            if (breakdown) {
-                status = BEMFFT_EBREAKDOWN;
-                set_error("GMRES: non-finite Hessenberg entry");
-                break;
-            }
-            // y = H^{-1} g (upper triangular, k x k)
-            for (int i = k - 1; i >= 0; --i) {
-                double s = g[i];
-                for (int j = i + 1; j < k; ++j) s -= H[(size_t)j * (mcap + 1) + i] * y[j];
-                double d = H[(size_t)i * (mcap + 1) + i];
-                y[i] = d != 0.0 ? s / d : 0.0;
-            }
-            // x += Dinv V y
-            BF_HIP(hipMemcpyAsync(ws.hd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-            BF_HIP(hipMemsetAsync(ws.r, 0, n * sizeof(double), st));
-            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k, ws.hd, ws.r, n, 1.0);
-            hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(256), 0, st, ws.r, ws.dinv, n);
-            hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.x, ws.r, 1.0, 1.0, n);
+            if (rel <= o.tol || bnorm == 0.0) { status = 0; break; }
+            if (outer >= o.max_outer || iters >= o.maxit) { status = BEMFFT_ENOCONV; break; }
+            // inner solve: no need to go below what the outer target still needs
+            const double itol = std::max(o.inner_tol, 0.5 * o.tol / rel);
+            int it = 0, rs = 0;
+            double irel = 0.0;
+            BF_HIP(hipMemsetAsync(ws.d, 0, n * sizeof(double), st));
+            int s3 = gmres_core(p, p->eng, bc, ws.ro, ws.d, true, itol, o.restart, o.maxit - iters, ws, hp, st, &it,
+                                &rs, &irel);
+            iters += it;
+            restarts += rs;
+            if (s3 < 0) { status = s3; break; }
+            hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.x, ws.d, 1.0, 1.0, n);
             BF_HIP(hipGetLastError());
             x_zero = false;
-            ++restarts;
+            ++outer;
         }
-        if (restarts > 0) --restarts;  // the first cycle is not a restart
     }
     BF_HIP(hipMemcpyAsync(unknown, ws.x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     BF_HIP(hipStreamSynchronize(st));
     if (info) {
         info->iters = iters;
         info->restarts = restarts;
-        info->true_relres = true_rel;
+        info->true_relres = rel;
         info->status = status;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->outer = outer;
+        info->applies64 = o.refine ? applies64 : 0;
     }
     return status;
 }

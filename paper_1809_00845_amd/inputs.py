@@ -281,17 +281,46 @@ def draw_stars(seed: int, count: int, rmin=0.1, rmax=0.45):
     return out
 
 
+def _theta_part(l, m, theta):
+    """theta factor of the real Y_lm (its phi factor is cos(m phi), 1 or
+    sin(|m| phi)); real_sph_harm = _theta_part * _phi_part."""
+    from scipy.special import sph_harm_y
+
+    v = np.real(sph_harm_y(l, abs(m), theta, np.zeros_like(theta)))
+    return v if m == 0 else math.sqrt(2.0) * (-1) ** m * v
+
+
+def _phi_part(m, phi, deriv=False):
+    if m == 0:
+        return np.zeros_like(phi) if deriv else np.ones_like(phi)
+    if m > 0:
+        return -m * np.sin(m * phi) if deriv else np.cos(m * phi)
+    k = -m
+    return k * np.cos(k * phi) if deriv else np.sin(k * phi)
+
+
 def star3d(n: int, spec: StarSpec, center=(0.5, 0.5, 0.5), ntheta=None, nphi=None) -> Geometry:
-    """Star-shaped surface ``r(theta, phi)`` voxelised on an ``n^3`` grid."""
+    """Star-shaped surface ``r(theta, phi)`` voxelised on an ``n^3`` grid.
+    Each real Y_lm factors into a theta part and a phi part, so r and its
+    derivatives on the quadrature grid are small matrix products."""
     nt, npf = _default_quadrature(n)
     ntheta, nphi = ntheta or nt, nphi or npf
     c = np.asarray(center, dtype=np.float64)
-    d = 1e-5
+    d = 1e-6
+    ph_all = (np.arange(nphi) + 0.5) * (2.0 * math.pi / nphi)
+    Pphi = np.stack([_phi_part(m, ph_all) for (l, m) in spec.lm])          # (6, nphi)
+    Pphi_d = np.stack([_phi_part(m, ph_all, True) for (l, m) in spec.lm])
+    coef = np.asarray(spec.coef)
 
     def surf(T, Ph):
-        r = spec.radius(T, Ph)
-        rt = (spec.radius(T + d, Ph) - spec.radius(T - d, Ph)) / (2 * d)
-        rp = (spec.radius(T, Ph + d) - spec.radius(T, Ph - d)) / (2 * d)
+        th = T[:, 0]
+        Th = np.stack([_theta_part(l, m, th) for (l, m) in spec.lm], 1)    # (nt, 6)
+        Th_d = np.stack([(_theta_part(l, m, th + d) - _theta_part(l, m, th - d)) / (2 * d)
+                         for (l, m) in spec.lm], 1)
+        s = (Th * coef) @ Pphi
+        r = spec.base * (1.0 + spec.amp * s)
+        rt = spec.base * spec.amp * ((Th_d * coef) @ Pphi)
+        rp = spec.base * spec.amp * ((Th * coef) @ Pphi_d)
         st, ct, sp, cp = np.sin(T), np.cos(T), np.sin(Ph), np.cos(Ph)
         er = np.stack([st * cp, st * sp, ct], axis=-1)
         et = np.stack([ct * cp, ct * sp, -st], axis=-1)

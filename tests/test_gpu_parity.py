@@ -36,13 +36,14 @@ def _t(a, dev):
     return torch.tensor(np.ascontiguousarray(a), device=dev)
 
 
-def _parity(dev, g, kernel, precision, cmode=B.C_IMPLICIT, seed=0, cuser=None, nu=0.3, mu=1.0, targets=None):
+def _parity(dev, g, kernel, precision, cmode=B.C_IMPLICIT, seed=0, cuser=None, nu=0.3, mu=1.0, targets=None,
+            autotune=0):
     nc = 3 if kernel == B.NAVIER3D else 1
     m = len(g.weights)
     rng = np.random.default_rng(seed)
     q = rng.uniform(-1, 1, (nc, m))
     u = rng.uniform(-1, 1, (nc, m))
-    plan = B.Plan(g, kernel, precision=precision, c_mode=cmode, c_user=cuser, nu=nu, mu=mu)
+    plan = B.Plan(g, kernel, precision=precision, c_mode=cmode, c_user=cuser, nu=nu, mu=mu, autotune=autotune)
     r = plan.apply(_t(q, dev), _t(u, dev))
     torch.cuda.synchronize()
     r = r.cpu().numpy().reshape(nc, m)
@@ -286,3 +287,70 @@ def test_solve_maxit_reports_noconv(dev):
     x, info = plan.solve(_t(bc, dev), _t(u, dev), tol=1e-14, maxit=3)
     assert info["status"] == B.ENOCONV and info["iters"] == 3
     assert np.isfinite(x.cpu().numpy()).all()
+
+
+def test_refined_fp32_solve_reaches_fp64_accuracy(dev):
+    """Iterative refinement: FP64 residuals, FP32 corrections.  The refined
+    solution of the mixed sphere problem matches the FP64 oracle's LU
+    solution to the FP64 GMRES bar, and its true FP64 residual meets tol."""
+    g = I.sphere3d(32, 0.35)
+    u, q = I.harmonic_3d_xyz(g)
+    bc = I.mixed_bc_upper(g)
+    known = np.where(bc == 0, u, q)
+    plan = B.Plan(g, B.LAPLACE3D, precision=B.FP32, keep_fp64=True)
+    x, info = plan.solve(_t(bc, dev), _t(known, dev), tol=1e-10, refine=1, inner_tol=1e-4)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-10 and info["outer"] >= 2
+    xl = O.solve_lu(O.problem(g, O.LAPLACE3D), bc, known)
+    assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
+    # without keep_fp64 a refined solve is rejected
+    plan2 = B.Plan(g, B.LAPLACE3D, precision=B.FP32)
+    with pytest.raises(B.BemfftError):
+        plan2.solve(_t(bc, dev), _t(known, dev), refine=1)
+
+
+def test_navier_refined_solve(dev):
+    g = I.sphere3d(16, 0.35)
+    nu, mu = 0.3, 1.0
+    lam = 2 * mu * nu / (1 - 2 * nu)
+    E = np.random.default_rng(8).normal(size=(3, 3))
+    Es = 0.5 * (E + E.T)
+    u = (g.rel() @ E.T).T
+    t = (g.normals @ (lam * np.trace(Es) * np.eye(3) + 2 * mu * Es).T).T
+    bc = np.tile(I.mixed_bc_upper(g), (3, 1))
+    known = np.where(bc == 0, u, t)
+    plan = B.Plan(g, B.NAVIER3D, precision=B.FP32, nu=nu, mu=mu, keep_fp64=True)
+    x, info = plan.solve(_t(bc, dev), _t(known, dev), tol=1e-9, refine=1)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-9
+    xl = O.solve_lu(O.problem(g, O.NAVIER3D, nu, mu), bc, known)
+    assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
+
+
+@pytest.mark.parametrize("n", [16, 32, 48, 64, 96, 128, 160, 192])
+def test_every_fft_length_both_schedules(dev, n):
+    """Sphere on n^3 (padded 2n: every compiled FFT length up to 384), FP32,
+    with the default and the alternative z schedule; oracle on a contiguous
+    sample of 300 targets."""
+    g = I.sphere3d(n, 0.35)
+    m = g.m
+    tg = (m // 3, min(m, m // 3 + 300))
+    for sched in (0, 2):
+        err, info = _parity(dev, g, B.LAPLACE3D, B.FP32, targets=tg, autotune=sched)
+        assert info["pad"][2] == 2 * n
+        assert info["zsched"] == (1 if sched == 2 else 0)
+        assert err < TOL[B.FP32], (n, sched, err)
+
+
+def test_navier_alternative_schedule(dev):
+    g = I.sphere3d(24, 0.35)
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.NAVIER3D, prec, autotune=2)
+        assert info["zsched"] == 1 and err < TOL[prec], (prec, err)
+
+
+def test_autotune_picks_a_schedule(dev):
+    g = I.sphere3d(64, 0.35)
+    plan = B.Plan(g, B.LAPLACE3D, precision=B.FP32, autotune=1)
+    info = plan.info()
+    assert info["zsched"] in (0, 1)
+    assert all(t > 0 for t in info["tune_us"])
+    assert info["tune_us"][info["zsched"]] == min(info["tune_us"])
