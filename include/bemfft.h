@@ -186,6 +186,43 @@ typedef struct {
 int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
                  const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
 
+/* ------------------------------------------------------------- batches
+ * Many boundaries and right-hand sides at once (the operator of eq. 4 / 8
+ * for each; nothing couples the members).  A member is (plan i, right-hand
+ * side j); all plans of a batch share the kernel family and working
+ * precision.  Device vectors of a batch concatenate the members' [ncomp][m_i]
+ * blocks in member order: plan 0 rhs 0, plan 0 rhs 1, ..., plan 1 rhs 0, ...
+ * (bemfft_batch_members gives each block's offset and length in doubles).
+ * The batch refers to its plans, which must outlive it, and owns one set of
+ * intermediates per member.
+ */
+typedef struct bemfft_batch bemfft_batch;
+
+/* Build a batch of nplans plans x nrhs right-hand sides.  Members of plans
+ * with equal padded sizes and z schedule share one launch per stage.  With
+ * use_graph = 1 the launch sequence is captured once into a HIP graph that
+ * every batched apply replays.  Errors: EINVAL (mixed families/precisions),
+ * ENOMEM, EDEVICE. */
+int bemfft_batch_create(bemfft_batch **out, bemfft_plan *const *plans, int nplans, int nrhs, int use_graph,
+                        void *stream);
+
+/* r = c u + D[u] - S[q] for every member (concatenated device vectors). */
+int bemfft_batch_apply(bemfft_batch *b, const double *q, const double *u, double *r, void *stream);
+
+/* The mixed problem of bemfft_solve for every member (bc, known, unknown
+ * concatenated), by restarted GMRES run for all members in lockstep: one
+ * batched apply per iteration; members leave when their own relative true
+ * residual meets tol.  info: NULL or one entry per member.  refine is not
+ * supported (EINVAL).  Returns 0, ENOCONV if any member stopped at maxit,
+ * EBREAKDOWN, EINVAL, EDEVICE. */
+int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, double *unknown,
+                       const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
+
+/* Member count; offsets/lengths (may be NULL) receive each member's block. */
+int bemfft_batch_members(const bemfft_batch *b, int64_t *offsets, int64_t *lengths);
+
+int bemfft_batch_destroy(bemfft_batch *b);
+
 /* Facts about a plan (host copies). */
 typedef struct {
     int dim, kernel, precision, c_mode;

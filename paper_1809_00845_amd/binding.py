@@ -57,7 +57,8 @@ class bemfft_plan_info(ctypes.Structure):
 EXPORTS = [
     "bemfft_plan_create", "bemfft_apply", "bemfft_apply_profile", "bemfft_solve", "bemfft_plan_get_info", "bemfft_plan_get_c",
     "bemfft_plan_destroy", "bemfft_fft3d_c2c_f64", "bemfft_strerror", "bemfft_last_error",
-    "bemfft_supported_sizes",
+    "bemfft_supported_sizes", "bemfft_batch_create", "bemfft_batch_apply", "bemfft_batch_solve",
+    "bemfft_batch_members", "bemfft_batch_destroy",
 ]
 
 _lib = None
@@ -93,6 +94,13 @@ def load():
     L.bemfft_strerror.restype = ctypes.c_char_p
     L.bemfft_last_error.restype = ctypes.c_char_p
     L.bemfft_supported_sizes.argtypes = [ctypes.POINTER(i64), ctypes.c_int]
+    L.bemfft_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, vp]
+    L.bemfft_batch_apply.argtypes = [vp, vp, vp, vp, vp]
+    L.bemfft_batch_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(bemfft_solve_opts),
+                                     ctypes.POINTER(bemfft_solve_info), vp]
+    L.bemfft_batch_members.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.bemfft_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -263,5 +271,50 @@ class Plan:
         try:
             if getattr(self, "handle", None) is not None:
                 self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many plans x right-hand sides applied/solved together (concatenated
+    device vectors; see bemfft_batch_* in include/bemfft.h)."""
+
+    def __init__(self, plans, nrhs=1, use_graph=True, stream=None):
+        self.plans = list(plans)  # keep the plans alive
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self.handle = ctypes.c_void_p()
+        _check(load().bemfft_batch_create(ctypes.byref(self.handle), arr, len(self.plans), int(nrhs),
+                                          1 if use_graph else 0, _stream_ptr(stream)), "bemfft_batch_create")
+        nm = len(self.plans) * nrhs
+        off = (ctypes.c_int64 * nm)()
+        ln = (ctypes.c_int64 * nm)()
+        load().bemfft_batch_members(self.handle, off, ln)
+        self.offsets = [int(v) for v in off]
+        self.lengths = [int(v) for v in ln]
+        self.total = self.offsets[-1] + self.lengths[-1]
+        self.nrhs = nrhs
+
+    def apply(self, q, u, r, stream=None):
+        return _check(load().bemfft_batch_apply(self.handle, _ptr(q), _ptr(u), _ptr(r), _stream_ptr(stream)),
+                      "bemfft_batch_apply")
+
+    def solve(self, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, precond=1, use_x0=0, stream=None):
+        nm = len(self.offsets)
+        o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0, 0, 1e-4, 20)
+        info = (bemfft_solve_info * nm)()
+        st = load().bemfft_batch_solve(self.handle, _ptr(bc), _ptr(known), _ptr(unknown), ctypes.byref(o), info,
+                                       _stream_ptr(stream))
+        _check(st, "bemfft_batch_solve")
+        return st, [{"iters": i.iters, "true_relres": i.true_relres, "status": i.status, "seconds": i.seconds}
+                    for i in info]
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load().bemfft_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -125,31 +125,17 @@ static int inv_kxc(int kernel, int precision, int py) {
 }
 
 int alloc_workspace(bemfft_plan *p, Engine *e) {
-    const size_t cb = 2 * e->creal;
-    const size_t rows = (size_t)p->H[0] * p->nzo * p->P[1];
-    const int kxc = inv_kxc(p->kernel, e->precision, (int)p->P[1]);
-    if (kxc <= 0) {
-        set_error("unsupported y length");
-        return BEMFFT_EUNSUPPORTED;
-    }
-    e->G = (int)((p->H[0] + kxc - 1) / kxc);
+    BF_CHECK(alloc_intermediates(p, e->precision, e));
     const size_t spec = (size_t)p->K * p->H[0] * p->H[1] * p->H[2] * e->creal;
-    const size_t ysz = (size_t)p->F * rows * cb, zsz = (size_t)p->O * rows * cb;
-    const size_t psz = (size_t)e->G * p->O * p->m * sizeof(double);
-    const size_t vsz = (size_t)p->F * p->m * e->creal;
-    const size_t xsz = std::max<size_t>(1, (size_t)p->nd * p->F * p->H[0] * cb);
-    if (hipMalloc(&e->spec, spec) != hipSuccess || hipMalloc(&e->Y, ysz) != hipSuccess ||
-        hipMalloc(&e->Z, zsz) != hipSuccess || hipMalloc(&e->partial, psz) != hipSuccess ||
-        hipMalloc(&e->vf, vsz) != hipSuccess || hipMalloc(&e->Xd, xsz) != hipSuccess) {
-        set_error("hipMalloc of the workspace failed");
+    if (hipMalloc(&e->spec, spec) != hipSuccess) {
+        set_error("hipMalloc of the spectra failed");
         return BEMFFT_ENOMEM;
     }
-    e->bytes = spec + ysz + zsz + psz + vsz + xsz;
+    e->bytes += spec;
     return 0;
 }
 
-int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double *u, double *r, hipStream_t st,
-                 hipEvent_t *ev) {
+void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, ApplyArgs *out) {
     ApplyArgs a{};
     a.nx = (int)p->n[0];
     a.ny = (int)p->n[1];
@@ -163,7 +149,7 @@ int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double 
     a.z0 = (int)p->z0;
     a.nzo = (int)p->nzo;
     a.m = (int)p->m;
-    a.G = e.G;
+    a.G = ws.G;
     a.gx = p->d_gx;
     a.gy = p->d_gy;
     a.rowptr = p->d_rowptr;
@@ -172,23 +158,57 @@ int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double 
     a.nrm = p->d_nrm;
     a.C = p->d_C;
     a.SC = p->d_SC;
-    a.q = q;
-    a.u = u;
-    a.r = r;
     a.spec = e.spec;
     a.twx = e.twx;
     a.twy = e.twy;
     a.twz = e.twz;
-    a.Y = e.Y;
-    a.Z = e.Z;
-    a.partial = e.partial;
-    a.vf = e.vf;
-    a.Xd = e.Xd;
+    a.Y = ws.Y;
+    a.Z = ws.Z;
+    a.partial = ws.partial;
+    a.vf = ws.vf;
+    a.Xd = ws.Xd;
     a.row_dense = p->d_row_dense;
     a.dense_rows = p->d_dense_rows;
     a.nd = (int)p->nd;
     a.node_splits = (int)std::max<int64_t>(1, (p->max_plane_nodes + kGatherChunk - 1) / kGatherChunk);
     a.zsched = p->zsched;
+    a.off = 0;
+    a.gid = 0;
+    *out = a;
+}
+
+int alloc_intermediates(const bemfft_plan *p, int precision, Engine *e) {
+    e->precision = precision;
+    e->creal = precision == BEMFFT_FP32 ? 4 : 8;
+    const size_t cb = 2 * e->creal;
+    const size_t rows = (size_t)p->H[0] * p->nzo * p->P[1];
+    const int kxc = inv_kxc(p->kernel, e->precision, (int)p->P[1]);
+    if (kxc <= 0) {
+        set_error("unsupported y length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    e->G = (int)((p->H[0] + kxc - 1) / kxc);
+    const size_t ysz = (size_t)p->F * rows * cb, zsz = (size_t)p->O * rows * cb;
+    const size_t psz = (size_t)e->G * p->O * p->m * sizeof(double);
+    const size_t vsz = (size_t)p->F * p->m * e->creal;
+    const size_t xsz = std::max<size_t>(1, (size_t)p->nd * p->F * p->H[0] * cb);
+    if (hipMalloc(&e->Y, ysz) != hipSuccess || hipMalloc(&e->Z, zsz) != hipSuccess ||
+        hipMalloc(&e->partial, psz) != hipSuccess || hipMalloc(&e->vf, vsz) != hipSuccess ||
+        hipMalloc(&e->Xd, xsz) != hipSuccess) {
+        set_error("hipMalloc of the intermediates failed");
+        return BEMFFT_ENOMEM;
+    }
+    e->bytes = ysz + zsz + psz + vsz + xsz;
+    return 0;
+}
+
+int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double *u, double *r, hipStream_t st,
+                 hipEvent_t *ev) {
+    ApplyArgs a;
+    fill_apply_args(p, e, e, &a);
+    a.q = q;
+    a.u = u;
+    a.r = r;
     if (p->kernel == 0) return apply_kind<0>(e.precision, a, st, ev);
     if (p->kernel == 1) return apply_kind<1>(e.precision, a, st, ev);
     return apply_kind<2>(e.precision, a, st, ev);

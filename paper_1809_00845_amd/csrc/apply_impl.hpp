@@ -39,6 +39,8 @@ struct ApplyArgs {
     int G;
     int node_splits;  // node chunks per plane in the gather
     int zsched;       // radix schedule of the z pass (0 or 1)
+    int64_t off;      // batched apply: offset of this member's q, u, r
+    int gid;          // batched apply: member index in the whole batch
     const int *gx, *gy, *rowptr, *perm;
     const double *w, *nrm, *C, *SC;
     const double *q, *u;
@@ -51,6 +53,22 @@ struct ApplyArgs {
     int nd;
     void *Y, *Z;
     double *partial;
+};
+
+// Launch extents of one group of batch members (same family, precision,
+// padded sizes and schedule): the largest per-member extents.
+struct GroupDims {
+    int nmem;
+    int max_m, max_nd, max_nzo, max_splits;
+    int G, hx, px, py, pz, zsched;
+};
+
+// Base pointers of a batched apply (device memory, so that a captured graph
+// of the launches serves any call) and the members still iterating.
+struct BatchIO {
+    const double *q, *u;
+    double *r;
+    const int *active;  // null: all members
 };
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -72,8 +90,8 @@ __device__ __forceinline__ int mod_small(int kx, int x, int p, float inv_p) {
 // Fig. 4 before it is placed on the grid): Laplace q w and u n_i w;
 // Navier t_j w and the symmetrised u (x) n w.
 template <typename R, int KIND>
-__global__ __launch_bounds__(256) void k_fields(ApplyArgs a) {
-    const int s = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void fields_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
+    const int s = bx * 256 + threadIdx.x;
     if (s >= a.m) return;
     R *vf = static_cast<R *>(a.vf);
     const int j = a.perm[s];
@@ -100,6 +118,22 @@ __global__ __launch_bounds__(256) void k_fields(ApplyArgs a) {
     }
 }
 
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_fields(ApplyArgs a) {
+    fields_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void kb_fields(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    fields_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+}
+
 // ------------------------------------------------------------------ k_rows_fft
 // Long grid rows (e.g. rows of a box face lying in a grid plane) are
 // x-transformed with an FFT instead of the direct sum: the row's nodes are
@@ -112,7 +146,7 @@ struct RowCfg {
 };
 
 template <typename R, int PX, int KIND>
-__global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
+__device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
     using Cfg = RowCfg<R, PX, KIND>;
     constexpr int TPP = Cfg::TPP, PPB = Cfg::PPB, E = PX / TPP, PS = pstride<PX>();
     constexpr int F = Terms<KIND>::F;
@@ -123,7 +157,7 @@ __global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
     const R *vf = static_cast<const R *>(a.vf);
     for (int i = tid; i < PX; i += 256) tw[i] = gtwx[i];
     const int pen = tid / TPP, t = tid % TPP;
-    const int pid = blockIdx.x * PPB + pen;  // (dense row, field)
+    const int pid = bx * PPB + pen;  // (dense row, field)
     const int d = pid / F, f = pid % F;
     const bool live = d < a.nd;
     cx<R> *pb = buf + pen * PS;
@@ -157,6 +191,22 @@ __global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
     }
 }
 
+template <typename R, int PX, int KIND>
+__global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
+    rows_fft_body<R, PX, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <typename R, int PX, int KIND>
+__global__ __launch_bounds__(256) void kb_rows_fft(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    rows_fft_body<R, PX, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+}
+
 // ------------------------------------------------------------------ k_fwd_xy
 template <typename R, int PY, int KIND>
 struct FwdCfg {
@@ -170,15 +220,16 @@ struct FwdCfg {
 };
 
 template <typename R, int PY, int KIND>
-__global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
+__device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
+    if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
     using Cfg = FwdCfg<R, PY, KIND>;
     constexpr int F = Cfg::F, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
     __shared__ cx<R> buf[F * KXC * PS];
     __shared__ cx<R> tw[PY];
     __shared__ cx<R> twx[kMaxPx];
     const int tid = threadIdx.x;
-    const int kx0 = blockIdx.x * KXC;
-    const int zz = blockIdx.y;
+    const int kx0 = bx * KXC;
+    const int zz = by;
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
     const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
     const R *vf = static_cast<const R *>(a.vf);
@@ -235,6 +286,22 @@ __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs 
     }
 }
 
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
+    fwd_xy_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void kb_fwd_xy(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    fwd_xy_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+}
+
 // ------------------------------------------------------------------ k_zpass
 // One wavefront owns PPW = 64/TPP pencils (consecutive ky at one kx) from
 // load to store; waves never wait for each other, so the loads of one wave
@@ -279,7 +346,7 @@ __device__ __forceinline__ void mac(cx<R> &acc, cx<R> v, R s, bool imag) {
 }
 
 template <typename R, typename SH, int KIND>
-__global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a) {
+__device__ __forceinline__ void zpass_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
     using Cfg = ZCfg<R, SH, KIND>;
     constexpr int PZ = SH::P;
     using T = Terms<KIND>;
@@ -289,9 +356,9 @@ __global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a) 
     __shared__ cx<R> tw[PZ];
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
-    const int kx = blockIdx.x;
+    const int kx = bx;
     const int b = lane / TPP, t = lane % TPP;
-    const int ky = blockIdx.y * TY + wave * PPW + b;
+    const int ky = by * TY + wave * PPW + b;
     const bool live = ky < a.py;
     cx<R> *pb = buf + (wave * PPW + b) * PS;
     const cx<R> *twz = static_cast<const cx<R> *>(a.twz);
@@ -343,13 +410,29 @@ __global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a) 
     }
 }
 
+template <typename R, typename SH, int KIND>
+__global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a) {
+    zpass_body<R, SH, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <typename R, typename SH, int KIND>
+__global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void kb_zpass(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    zpass_body<R, SH, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+}
+
 // 2D: the third axis has length 1, so the "z pass" is the spectral product.
 template <typename R, int KIND>
-__global__ __launch_bounds__(256) void k_mac2d(ApplyArgs a) {
+__device__ __forceinline__ void mac2d_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
     using T = Terms<KIND>;
     constexpr int O = T::O;
-    const int kx = blockIdx.x;
-    const int ky = blockIdx.y * 256 + threadIdx.x;
+    const int kx = bx;
+    const int ky = by * 256 + threadIdx.x;
     if (ky >= a.py) return;
     const cx<R> *Y = static_cast<const cx<R> *>(a.Y);
     cx<R> *Z = static_cast<cx<R> *>(a.Z);
@@ -367,6 +450,22 @@ __global__ __launch_bounds__(256) void k_mac2d(ApplyArgs a) {
     for (int o = 0; o < O; ++o) Z[(size_t)(o * a.hx + kx) * a.py + ky] = acc[o];
 }
 
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_mac2d(ApplyArgs a) {
+    mac2d_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void kb_mac2d(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    mac2d_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+}
+
 // ------------------------------------------------------------------ k_inv_yx
 template <typename R, int PY, int KIND>
 struct InvCfg {
@@ -379,19 +478,20 @@ struct InvCfg {
 };
 
 template <typename R, int PY, int KIND>
-__global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs a) {
+__device__ __forceinline__ void inv_yx_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
+    if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
     using Cfg = InvCfg<R, PY, KIND>;
     constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
     __shared__ cx<R> buf[O * KXC * PS];
     __shared__ cx<R> tw[PY];
     __shared__ cx<R> twx[kMaxPx];
     const int tid = threadIdx.x;
-    const int g = blockIdx.x;
+    const int g = bx;
     const int kx0 = g * KXC;
-    const int zz = blockIdx.y;
+    const int zz = by;
     // this block's share of the plane's nodes; empty shares leave at once
     const int p0 = a.rowptr[zz * a.ny], p1 = a.rowptr[(zz + 1) * a.ny];
-    const int s0 = p0 + blockIdx.z * kGatherChunk;
+    const int s0 = p0 + bz * kGatherChunk;
     const int s1 = min(p1, s0 + kGatherChunk);
     if (s0 >= s1) return;
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
@@ -440,10 +540,26 @@ __global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs 
     }
 }
 
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs a) {
+    inv_yx_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void kb_inv_yx(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    inv_yx_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+}
+
 // ------------------------------------------------------------------ epilogue
 template <int O>
-__global__ __launch_bounds__(256) void k_epilogue(ApplyArgs a) {
-    const int s = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void epilogue_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
+    const int s = bx * 256 + threadIdx.x;
     if (s >= a.m) return;
     const int j = a.perm[s];
 #pragma unroll
@@ -457,6 +573,22 @@ __global__ __launch_bounds__(256) void k_epilogue(ApplyArgs a) {
         }
         a.r[o * a.m + j] = v;
     }
+}
+
+template <int O>
+__global__ __launch_bounds__(256) void k_epilogue(ApplyArgs a) {
+    epilogue_body<O>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
+template <int O>
+__global__ __launch_bounds__(256) void kb_epilogue(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    ApplyArgs a = members[blockIdx.z / zdiv];
+    if (io->active && !io->active[a.gid]) return;
+    a.q = io->q + a.off;
+    a.u = io->u + a.off;
+    a.r = io->r + a.off;
+    epilogue_body<O>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -542,6 +674,116 @@ struct Launch {
         set_error("unsupported y length");
         return BEMFFT_EUNSUPPORTED;
     }
+    // ---- batched: one launch per stage for all members of a group
+    template <int P> static int bfwd(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        using Cfg = FwdCfg<R, P, KIND>;
+        dim3 grid((g.hx + Cfg::KXC - 1) / Cfg::KXC, g.max_nzo, g.nmem);
+        hipLaunchKernelGGL((kb_fwd_xy<R, P, KIND>), grid, dim3(Cfg::NT), 0, st, dm, io, 1);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    template <int P> static int brows(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        using Cfg = RowCfg<R, P, KIND>;
+        dim3 grid((Terms<KIND>::F * g.max_nd + Cfg::PPB - 1) / Cfg::PPB, 1, g.nmem);
+        hipLaunchKernelGGL((kb_rows_fft<R, P, KIND>), grid, dim3(256), 0, st, dm, io, 1);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    template <int P> static int binv(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        using Cfg = InvCfg<R, P, KIND>;
+        dim3 grid(g.G, g.max_nzo, g.nmem * g.max_splits);
+        hipLaunchKernelGGL((kb_inv_yx<R, P, KIND>), grid, dim3(Cfg::NT), 0, st, dm, io, g.max_splits);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    template <int PZ, int SCHED>
+    static int bz_s(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        if constexpr (PZ == 1) {
+            dim3 grid(g.hx, (g.py + 255) / 256, g.nmem);
+            hipLaunchKernelGGL((kb_mac2d<R, KIND>), grid, dim3(256), 0, st, dm, io, 1);
+        } else {
+            using SH = Sched<PZ, SCHED>;
+            using Cfg = ZCfg<R, SH, KIND>;
+            dim3 grid(g.hx, (g.py + Cfg::TY - 1) / Cfg::TY, g.nmem);
+            hipLaunchKernelGGL((kb_zpass<R, SH, KIND>), grid, dim3(Cfg::NT), 0, st, dm, io, 1);
+        }
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    template <int P> static int bz(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        return g.zsched ? bz_s<P, 1>(dm, io, g, st) : bz_s<P, 0>(dm, io, g, st);
+    }
+    static int run_batch(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        hipLaunchKernelGGL((kb_fields<R, KIND>), dim3((g.max_m + 255) / 256, 1, g.nmem), dim3(256), 0, st, dm, io, 1);
+        BF_HIP(hipGetLastError());
+        if (g.max_nd > 0) {
+            int s2 = BEMFFT_EUNSUPPORTED;
+            switch (g.px) {
+                case 32: s2 = brows<32>(dm, io, g, st); break;
+                case 64: s2 = brows<64>(dm, io, g, st); break;
+                case 96: s2 = brows<96>(dm, io, g, st); break;
+                case 128: s2 = brows<128>(dm, io, g, st); break;
+                case 192: s2 = brows<192>(dm, io, g, st); break;
+                case 256: s2 = brows<256>(dm, io, g, st); break;
+                case 320: s2 = brows<320>(dm, io, g, st); break;
+                case 384: s2 = brows<384>(dm, io, g, st); break;
+                case 512: s2 = brows<512>(dm, io, g, st); break;
+                default: break;
+            }
+            BF_CHECK(s2);
+        }
+        int s3 = BEMFFT_EUNSUPPORTED;
+        switch (g.py) {
+            case 32: s3 = bfwd<32>(dm, io, g, st); break;
+            case 64: s3 = bfwd<64>(dm, io, g, st); break;
+            case 96: s3 = bfwd<96>(dm, io, g, st); break;
+            case 128: s3 = bfwd<128>(dm, io, g, st); break;
+            case 192: s3 = bfwd<192>(dm, io, g, st); break;
+            case 256: s3 = bfwd<256>(dm, io, g, st); break;
+            case 320: s3 = bfwd<320>(dm, io, g, st); break;
+            case 384: s3 = bfwd<384>(dm, io, g, st); break;
+            case 512: s3 = bfwd<512>(dm, io, g, st); break;
+            default: break;
+        }
+        BF_CHECK(s3);
+        int s4 = BEMFFT_EUNSUPPORTED;
+        if constexpr (KIND == 0) {
+            if (g.pz == 1) s4 = bz_s<1, 0>(dm, io, g, st);
+        } else {
+            switch (g.pz) {
+                case 32: s4 = bz<32>(dm, io, g, st); break;
+                case 64: s4 = bz<64>(dm, io, g, st); break;
+                case 96: s4 = bz<96>(dm, io, g, st); break;
+                case 128: s4 = bz<128>(dm, io, g, st); break;
+                case 192: s4 = bz<192>(dm, io, g, st); break;
+                case 256: s4 = bz<256>(dm, io, g, st); break;
+                case 320: s4 = bz<320>(dm, io, g, st); break;
+                case 384: s4 = bz<384>(dm, io, g, st); break;
+                case 512: s4 = bz<512>(dm, io, g, st); break;
+                default: break;
+            }
+        }
+        BF_CHECK(s4);
+        int s5 = BEMFFT_EUNSUPPORTED;
+        switch (g.py) {
+            case 32: s5 = binv<32>(dm, io, g, st); break;
+            case 64: s5 = binv<64>(dm, io, g, st); break;
+            case 96: s5 = binv<96>(dm, io, g, st); break;
+            case 128: s5 = binv<128>(dm, io, g, st); break;
+            case 192: s5 = binv<192>(dm, io, g, st); break;
+            case 256: s5 = binv<256>(dm, io, g, st); break;
+            case 320: s5 = binv<320>(dm, io, g, st); break;
+            case 384: s5 = binv<384>(dm, io, g, st); break;
+            case 512: s5 = binv<512>(dm, io, g, st); break;
+            default: break;
+        }
+        BF_CHECK(s5);
+        hipLaunchKernelGGL((kb_epilogue<Terms<KIND>::O>), dim3((g.max_m + 255) / 256, 1, g.nmem), dim3(256), 0, st, dm,
+                           io, 1);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+
     static int dispatch_rows(const ApplyArgs &a, hipStream_t st) {
         BF_SIZE_SWITCH(a.px, rows, a, st);
         set_error("unsupported x length");
@@ -574,5 +816,14 @@ template <int KIND>
 int apply_kind(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t *ev);
 template <int KIND>
 int inv_kxc_kind(int precision, int py);
+template <int KIND>
+int apply_batch_kind(int precision, const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st);
+
+// Apply arguments of plan p with the spectra/tables of 'shared' and the
+// intermediate buffers of 'ws' (q, u, r left null).
+void fill_apply_args(const bemfft_plan *p, const Engine &shared, const Engine &ws, ApplyArgs *a);
+// Intermediate buffers of one apply of plan p (Y, Z, partial, fields, long
+// rows), without spectra or tables.
+int alloc_intermediates(const bemfft_plan *p, int precision, Engine *e);
 
 }  // namespace bemfft

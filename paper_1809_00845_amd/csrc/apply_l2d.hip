@@ -15,4 +15,10 @@ int inv_kxc_kind<0>(int precision, int py) {
     return Launch<double, 0>::inv_kxc(py);
 }
 
+template <>
+int apply_batch_kind<0>(int precision, const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+    if (precision == BEMFFT_FP32) return Launch<float, 0>::run_batch(dm, io, g, st);
+    return Launch<double, 0>::run_batch(dm, io, g, st);
+}
+
 }  // namespace bemfft

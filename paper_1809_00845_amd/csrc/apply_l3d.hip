@@ -15,4 +15,10 @@ int inv_kxc_kind<1>(int precision, int py) {
     return Launch<double, 1>::inv_kxc(py);
 }
 
+template <>
+int apply_batch_kind<1>(int precision, const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+    if (precision == BEMFFT_FP32) return Launch<float, 1>::run_batch(dm, io, g, st);
+    return Launch<double, 1>::run_batch(dm, io, g, st);
+}
+
 }  // namespace bemfft

@@ -354,3 +354,107 @@ def test_autotune_picks_a_schedule(dev):
     assert info["zsched"] in (0, 1)
     assert all(t > 0 for t in info["tune_us"])
     assert info["tune_us"][info["zsched"]] == min(info["tune_us"])
+
+
+# ------------------------------------------------------------------ batches
+
+
+def _mixed_batch_inputs(geoms, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    qs, us = [], []
+    for g in geoms:
+        for _ in range(nrhs):
+            qs.append(rng.uniform(-1, 1, g.m))
+            us.append(rng.uniform(-1, 1, g.m))
+    return np.concatenate(qs), np.concatenate(us)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_apply_matches_single_plans(dev, use_graph):
+    """Shapes on three grid sizes (two share a size), two right-hand sides
+    each: the batched apply (graph replayed three times, with eager work in
+    between) equals each plan's own apply bit for bit, and the oracle."""
+    specs = I.draw_stars(2, 3)
+    geoms = [I.star3d(24, specs[0], ntheta=384, nphi=768), I.star3d(32, specs[1], ntheta=512, nphi=1024),
+             I.star3d(24, specs[2], ntheta=384, nphi=768)]
+    plans = [B.Plan(g, B.LAPLACE3D, precision=B.FP32) for g in geoms]
+    nrhs = 2
+    batch = B.Batch(plans, nrhs=nrhs, use_graph=use_graph)
+    q, u = _mixed_batch_inputs(geoms, nrhs, 5)
+    qd, ud = _t(q, dev), _t(u, dev)
+    # reference: each member through its own plan
+    ref = []
+    k = 0
+    for g, p in zip(geoms, plans):
+        for _ in range(nrhs):
+            o, n = batch.offsets[k], batch.lengths[k]
+            ref.append(p.apply(qd[o:o + n].contiguous(), ud[o:o + n].contiguous()).cpu().numpy())
+            k += 1
+    ref = np.concatenate(ref)
+    for rep in range(3):
+        r = torch.full_like(qd, float("nan"))
+        batch.apply(qd, ud, r)
+        torch.cuda.synchronize()
+        got = r.cpu().numpy()
+        assert np.array_equal(got, ref), rep
+        _ = (qd * 2.0).sum().item()  # eager work between replays
+    # one member against the oracle
+    o, n = batch.offsets[3], batch.lengths[3]
+    p = O.problem(geoms[1], O.LAPLACE3D)
+    rr, sc = O.apply(p, q[o:o + n], u[o:o + n], with_scale=True)
+    assert np.abs(ref[o:o + n] - rr).max() / sc.max() < TOL[B.FP32]
+    batch.close()
+
+
+def test_batch_solve_matches_single_solves(dev):
+    """Batched lockstep GMRES on mixed problems (Dirichlet above the centre,
+    harmonic data of degree <= 3): every member takes the same iterations as
+    its own single-plan solve, meets the tolerance, and agrees with the
+    oracle's LU solution."""
+    specs = I.draw_stars(2, 2)
+    geoms = [I.star3d(16, specs[0], ntheta=256, nphi=512), I.star3d(24, specs[1], ntheta=384, nphi=768)]
+    plans = [B.Plan(g, B.LAPLACE3D, precision=B.FP64) for g in geoms]
+    nrhs = 2
+    batch = B.Batch(plans, nrhs=nrhs)
+    rng = np.random.default_rng(9)
+    known, bcs, refs, singles = [], [], [], []
+    for g, pl in zip(geoms, plans):
+        p = O.problem(g, O.LAPLACE3D)
+        bc = I.mixed_bc_upper(g)
+        for _ in range(nrhs):
+            u, q = I.random_harmonic_3d(g, rng)
+            kn = np.where(bc == 0, u, q)
+            known.append(kn)
+            bcs.append(bc)
+            refs.append(O.solve_lu(p, bc, kn))
+            _, si = pl.solve(_t(bc, dev), _t(kn, dev), tol=1e-10)
+            singles.append(si)
+    known = np.concatenate(known)
+    bcs = np.concatenate(bcs)
+    x = torch.zeros(batch.total, dtype=torch.float64, device=dev)
+    st, info = batch.solve(_t(bcs, dev), _t(known, dev), x, tol=1e-10)
+    assert st == 0, info
+    x = x.cpu().numpy()
+    for k, ref in enumerate(refs):
+        o, n = batch.offsets[k], batch.lengths[k]
+        assert info[k]["status"] == 0 and info[k]["true_relres"] <= 1e-10
+        assert abs(info[k]["iters"] - singles[k]["iters"]) <= 1, (info[k], singles[k])
+        assert np.linalg.norm(x[o:o + n] - ref) / np.linalg.norm(ref) < 1e-6
+    batch.close()
+
+
+def test_dirichlet_star_single_vs_batch_iterations(dev):
+    """First-kind (all Dirichlet) problem: report-only comparison that the
+    batched and single solves take the same path."""
+    spec = I.draw_stars(2, 1)[0]
+    g = I.star3d(16, spec, ntheta=256, nphi=512)
+    pl = B.Plan(g, B.LAPLACE3D, precision=B.FP64)
+    u, _ = I.random_harmonic_3d(g, np.random.default_rng(1))
+    bc = np.zeros(g.m, dtype=np.uint8)
+    _, si = pl.solve(_t(bc, dev), _t(u, dev), tol=1e-8, restart=200, maxit=400)
+    batch = B.Batch([pl], nrhs=1)
+    x = torch.zeros(batch.total, dtype=torch.float64, device=dev)
+    st, info = batch.solve(_t(bc, dev), _t(u, dev), x, tol=1e-8, restart=200, maxit=400)
+    assert st == si["status"]
+    assert abs(info[0]["iters"] - si["iters"]) <= 1, (info[0], si)
+    batch.close()
