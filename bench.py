@@ -99,6 +99,108 @@ def cpu_baseline(geom, q, u, budget_s=12.0):
                       f"{dt:.1f} s, scaled to one full apply ({full:.1f} s)"}
 
 
+def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
+    """64 star surfaces (seed 2) on grids drawn from {64, 96, 128, 160}^3,
+    4 right-hand sides each (Dirichlet data from random harmonic polynomials
+    of degree <= 3), FP32: batched apply (graph replay) and batched lockstep
+    GMRES to 1e-6, against per-plan applies and sequential plain FP64 solves."""
+    import tempfile
+
+    import torch
+
+    t0 = time.perf_counter()
+    items = I.draw_batch(2, count)
+    geoms = I.star_batch(items)
+    t_geom = time.perf_counter() - t0
+    tune = tempfile.NamedTemporaryFile(prefix="bemfft_tune_", delete=False)
+    tune.close()
+    os.environ["BEMFFT_TUNE_CACHE"] = tune.name
+    t0 = time.perf_counter()
+    plans = [B.Plan(g, B.LAPLACE3D, precision=B.FP32, autotune=1) for g in geoms]
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = B.Batch(plans, nrhs=nrhs, use_graph=True)
+    t_batch = time.perf_counter() - t0
+    rng = np.random.default_rng(20)
+    known, bcs = [], []
+    for g in geoms:
+        for _ in range(nrhs):
+            u, _ = I.random_harmonic_3d(g, rng)
+            known.append(u)
+            bcs.append(np.zeros(g.m, dtype=np.uint8))
+    known = torch.tensor(np.concatenate(known), device=dev)
+    bcs = torch.tensor(np.concatenate(bcs), device=dev)
+    q = torch.zeros_like(known)
+    r = torch.empty_like(known)
+    nm = len(batch.offsets)
+    for _ in range(3):
+        batch.apply(q, known, r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.apply(q, known, r)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / steps
+    # the same members one plan call at a time
+    views = [(p, batch.offsets[k], batch.lengths[k]) for k, p in
+             enumerate([pl for pl in plans for _ in range(nrhs)])]
+    qv = [q[o:o + n] for _, o, n in views]
+    uv = [known[o:o + n] for _, o, n in views]
+    rv = [r[o:o + n] for _, o, n in views]
+    for (p, _, _), a, b_, c in zip(views, qv, uv, rv):
+        p.apply(a, b_, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(2, steps // 5)
+    for _ in range(reps):
+        for (p, _, _), a, b_, c in zip(views, qv, uv, rv):
+            p.apply(a, b_, c)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / reps
+    # batched FP32 solve vs sequential plain FP64 solves
+    x = torch.zeros_like(known)
+    t0 = time.perf_counter()
+    st, sinfo = batch.solve(bcs, known, x, tol=1e-6, restart=100, maxit=1000)
+    torch.cuda.synchronize()
+    t_bsolve = time.perf_counter() - t0
+    its = [i["iters"] for i in sinfo]
+    t_seq = 0.0
+    seq_its = []
+    for g, p32 in zip(geoms, plans):
+        p64 = B.Plan(g, B.LAPLACE3D, precision=B.FP64)
+        for k in range(nrhs):
+            kk = len(seq_its)
+            o, n = batch.offsets[kk], batch.lengths[kk]
+            bck = bcs[o:o + n].contiguous()
+            knk = known[o:o + n].contiguous()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, si = p64.solve(bck, knk, tol=1e-6, restart=100, maxit=1000)
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t1
+            seq_its.append(si["iters"])
+        p64.close()
+    os.unlink(tune.name)
+    sizes = sorted(set(n for n, _ in items))
+    out = {
+        "workload": "64 star surfaces (seed 2), grids {64,96,128,160}^3 padded 2N, 4 Dirichlet RHS each, FP32",
+        "members": nm, "nodes_total": int(sum(g.m for g in geoms)),
+        "grid_counts": {str(n): sum(1 for m_, _ in items if m_ == n) for n in sizes},
+        "groups_by_pad_and_schedule": len(set((p.info()["pad"][0], p.info()["zsched"]) for p in plans)),
+        "batched_apply_ms": dt_b * 1e3, "batched_rhs_matvec_s": nm / dt_b,
+        "per_plan_apply_ms": dt_s * 1e3, "per_plan_rhs_matvec_s": nm / dt_s,
+        "batched_solve_fp32_s": t_bsolve, "batched_solve_status": st,
+        "batched_solve_iters_max": int(max(its)), "batched_solve_iters_mean": float(np.mean(its)),
+        "batched_solve_relres_max": float(max(i["true_relres"] for i in sinfo)),
+        "sequential_fp64_solves_s": t_seq, "sequential_fp64_iters_mean": float(np.mean(seq_its)),
+        "setup_s": {"voxelise": t_geom, "plans": t_plan, "batch_and_graph": t_batch},
+    }
+    batch.close()
+    for p in plans:
+        p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="apply timing only (for profilers)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-shape batched workload")
+    ap.add_argument("--batched-only", action="store_true", help="only the 64-shape batched workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB read + 256 MiB write kernel (counter calibration)")
     args = ap.parse_args()
@@ -130,6 +234,9 @@ def main():
 
     B.load()  # raises if the HIP library is missing
     dev = torch.device("cuda:0")
+    if args.batched_only:
+        print(json.dumps(bench_batched(B, I, dev)), flush=True)
+        return
     cube = I.cube3d(128, 100)
     uh, qh = I.harmonic_3d_xyz(cube)
     noise = I.uniform_noise(cube.m, 0, 2)
@@ -212,6 +319,9 @@ def main():
                                            "status": si["status"]}
         extra["time_to_solve_1e-6"] = solves
         extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
+        if not args.no_batched:
+            plan64.close()
+            extra["batched_64_stars_4rhs"] = bench_batched(B, I, dev)
         out["extra"] = extra
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline(cube, qn, un)

@@ -299,6 +299,45 @@ def _phi_part(m, phi, deriv=False):
     return k * np.cos(k * phi) if deriv else np.sin(k * phi)
 
 
+def draw_batch(seed: int, count: int, sizes=(64, 96, 128, 160), rmin=0.1, rmax=0.45):
+    """``count`` (grid size, star) pairs: the grid size uniform over
+    ``sizes``, then the star drawn as in draw_stars, all from one stream."""
+    rng = np.random.default_rng(seed)
+    tt, pp = np.meshgrid(np.linspace(0, math.pi, 91), np.linspace(0, 2 * math.pi, 181), indexing="ij")
+    out = []
+    while len(out) < count:
+        n = int(sizes[rng.integers(len(sizes))])
+        while True:
+            idx = rng.choice(25, 6, replace=False)
+            coef = rng.standard_normal(6)
+            spec = StarSpec([_LM[i] for i in idx], coef)
+            r = spec.radius(tt, pp)
+            if rmin < r.min() and r.max() < rmax:
+                break
+        out.append((n, spec))
+    return out
+
+
+def _star_job(args):
+    n, spec, q = args
+    return star3d(n, spec, ntheta=q * n, nphi=2 * q * n)
+
+
+def star_batch(items, quad_per_cell: int = 8, workers: int | None = None):
+    """Voxelise many (n, spec) pairs in parallel processes; quadrature of
+    quad_per_cell*n x 2*quad_per_cell*n points per shape."""
+    import multiprocessing as mp
+    import os
+
+    if workers is None:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    jobs = [(n, spec, quad_per_cell) for n, spec in items]
+    if workers == 1:
+        return [_star_job(j) for j in jobs]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_star_job, jobs, chunksize=1)
+
+
 def star3d(n: int, spec: StarSpec, center=(0.5, 0.5, 0.5), ntheta=None, nphi=None) -> Geometry:
     """Star-shaped surface ``r(theta, phi)`` voxelised on an ``n^3`` grid.
     Each real Y_lm factors into a theta part and a phi part, so r and its
