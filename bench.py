@@ -201,6 +201,71 @@ def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
     return out
 
 
+def bench_learned(B, args):
+    """Learned start: a 4-layer, 16-channel dilated conv net on the G^3 grid,
+    trained on the GPU with the library's kernels on star problems (seed 3)
+    solved by the library's FP64 GMRES, then GMRES to 1e-6 from the learned
+    start (use_x0 = 2) against GMRES from zero on held-out problems."""
+    import torch
+
+    from paper_1809_00845_amd import learned as LS
+
+    G, ntr, nte = args.learned_grid, args.learned_train, args.learned_test
+    t0 = time.perf_counter()
+    probs = LS.problem_set(G, ntr + nte, seed=3)
+    t_geom = time.perf_counter() - t0
+    print(f"  voxelised {ntr + nte} stars at {G}^3 in {t_geom:.1f} s", flush=True)
+    net = B.Net(G, (1, 2, 4, 8), seed=0)
+    t0 = time.perf_counter()
+    train = LS.make_samples(net, probs[:ntr], progress=200)
+    test_s = LS.make_samples(net, probs[ntr:], progress=100)
+    t_data = time.perf_counter() - t0
+    e0 = LS.relative_error(net, test_s)
+    # one training step, timed alone
+    s = train[0]
+    for _ in range(3):
+        net.gradients(s.x, s.vox, s.tgt, s.wt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        net.gradients(s.x, s.vox, s.tgt, s.wt)
+    t_grad = (time.perf_counter() - t0) / 10
+    t0 = time.perf_counter()
+    hist = LS.train(net, train, epochs=args.learned_epochs, lr=2e-3)
+    t_train = time.perf_counter() - t0
+    e1 = LS.relative_error(net, test_s)
+    del train, test_s
+    # inference alone
+    xb = torch.empty((6, net.V), dtype=torch.float32, device="cuda:0")
+    yb = torch.empty(net.V, dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        net.forward(xb.zero_(), yb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        net.forward(xb, yb)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / 20
+    t0 = time.perf_counter()
+    rows = LS.evaluate(net, probs[ntr:])
+    t_eval = time.perf_counter() - t0
+    sm = LS.summary(rows)
+    net.close()
+    return {
+        "workload": f"learned start: star surfaces (seed 3) on {G}^3, pad {2 * G}^3, Laplace Dirichlet, "
+                    f"{ntr} train / {nte} held-out, GMRES(100) right Jacobi to 1e-6, FP64",
+        "network": "conv3d 3x3x3 dilations 1,2,4,8; 6->16->16->16->1; ReLU; FP32",
+        "params": net.nparam,
+        "epochs": args.learned_epochs,
+        "test_rel_sq_error_before": e0, "test_rel_sq_error_after": e1,
+        "train_loss_per_epoch": hist,
+        "ms_per_train_step": 1e3 * t_grad,
+        "ms_per_forward": 1e3 * t_fwd,
+        "seconds": {"voxelise": t_geom, "solve_and_inputs": t_data, "train": t_train, "evaluate": t_eval},
+        **sm,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +275,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="apply timing only (for profilers)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-shape batched workload")
     ap.add_argument("--batched-only", action="store_true", help="only the 64-shape batched workload")
+    ap.add_argument("--learned", action="store_true",
+                    help="only the learned-start workload: train on GPU-solved star problems, then compare solves")
+    ap.add_argument("--learned-grid", type=int, default=96)
+    ap.add_argument("--learned-train", type=int, default=2000)
+    ap.add_argument("--learned-test", type=int, default=200)
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB read + 256 MiB write kernel (counter calibration)")
     args = ap.parse_args()
@@ -236,6 +307,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.batched_only:
         print(json.dumps(bench_batched(B, I, dev)), flush=True)
+        return
+    if args.learned:
+        print(json.dumps(bench_learned(B, args)), flush=True)
         return
     cube = I.cube3d(128, 100)
     uh, qh = I.harmonic_3d_xyz(cube)

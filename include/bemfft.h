@@ -146,7 +146,9 @@ typedef struct {
     int restart;    /* Krylov basis size (default 100, max 400)               */
     int maxit;      /* total iterations (default 1000)                        */
     int precond;    /* 0 none, 1 Jacobi (default 1)                           */
-    int use_x0;     /* 1: 'unknown' holds the initial guess on entry          */
+    int use_x0;     /* 0: start from x = 0; 1: 'unknown' holds the initial
+                       guess on entry; 2: as 1, but the guess is kept only
+                       if ||b - A x0|| < ||b|| (else x = 0: plain GMRES)  */
     int refine;     /* 1: iterative refinement -- residuals r = b - A x with
                        the plan's FP64 operator (plan made with keep_fp64),
                        corrections from GMRES with the plan's working
@@ -164,6 +166,8 @@ typedef struct {
     double seconds;     /* wall time of the call                              */
     int outer;          /* refinement steps (0 without refine)                */
     int applies64;      /* FP64 applications made by the refinement            */
+    int x0_used;        /* 1 if the solve started from the caller's guess      */
+    double x0_relres;   /* use_x0 = 2: ||b - A x0|| / ||b|| of the guess, else -1 */
 } bemfft_solve_info;
 
 /*
@@ -245,6 +249,73 @@ int bemfft_plan_get_c(const bemfft_plan *p, double *c_host);
 
 /* Release all device state of the plan.  NULL is accepted. */
 int bemfft_plan_destroy(bemfft_plan *p);
+
+/* ------------------------------------------------------ learned start
+ * A small 3D convolutional network that maps a Dirichlet problem (Sec. 4:
+ * u given on the boundary, q sought) to an initial guess of q for
+ * bemfft_solve (use_x0 = 2 keeps the guess only if it beats x = 0).  This
+ * is an addition to the method, not part of the paper.
+ *   Input channels on the plan's n^3 grid (zero off the boundary), summed
+ *   over the nodes of a voxel: a = w/h^2; a n_x; a n_y; a n_z; a s u; a s b
+ *   (u the Dirichlet value, s = 1/rms(u) over the Dirichlet slots, b the
+ *   right-hand side of bemfft_solve: minus the operator applied to the
+ *   known values, computed with one application of the plan).
+ *   Layers: 3x3x3 convolutions with per-layer dilation (zero padding),
+ *   6 -> 16 -> ... -> 16 -> 1 channels, bias, ReLU on all but the last.
+ *   Output y: one channel; the guess is q_j = y(voxel of node j) / (s h)
+ *   (training targets are s h q_j: a flux per voxel length).
+ * Parameters are FP32, laid out per layer as W[cout][cin][27] (tap index
+ * (dz+1)*9 + (dy+1)*3 + (dx+1)) followed by b[cout].  Arithmetic and
+ * activations are FP32.  Training minimises sum_i wt_i (y(vox_i) - t_i)^2
+ * with Adam (beta 0.9 / 0.999, eps 1e-8).  A network owns its activations
+ * (2 * layers * 16 * n^3 floats) and is used by one stream at a time.
+ */
+typedef struct bemfft_net bemfft_net;
+
+/* grid in [4, 256], width 16, layers in [2, 8], dilations[layers] >= 1.
+ * Weights: He-normal from a 64-bit Mersenne twister with 'seed' (the last
+ * layer scaled by 0.1), biases 0.  Errors: EINVAL, ENOMEM. */
+int bemfft_net_create(bemfft_net **out, int grid, int width, int layers, const int *dilations,
+                      uint64_t seed, void *stream);
+int bemfft_net_destroy(bemfft_net *n);
+int64_t bemfft_net_num_params(const bemfft_net *n);
+/* host <-> device copies of the parameter vector (num_params floats) */
+int bemfft_net_get_params(const bemfft_net *n, float *params_host);
+int bemfft_net_set_params(bemfft_net *n, const float *params_host);
+
+/* Input channels of a problem: x device [6][n^3] floats (overwritten).  The
+ * plan must be LAPLACE3D on the network's grid; bc/known as for
+ * bemfft_solve (bc may be NULL: all Dirichlet); scale is s.  Runs one
+ * apply of the plan on 'stream' (network-owned scratch of 3m doubles,
+ * grown on demand).  Errors: EINVAL, ENOMEM, EDEVICE. */
+int bemfft_net_input(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const double *known,
+                     double scale, float *x, void *stream);
+
+/* y device [n^3] = network(x). */
+int bemfft_net_forward(bemfft_net *n, const float *x, float *y, void *stream);
+
+/* Loss sum_i wt_i (y(vox_i) - tgt_i)^2 of input x (all device arrays, nt
+ * targets, vox = z*n*n + y*n + x) and its gradient with respect to every
+ * parameter (written to grad_host if not NULL, num_params floats).
+ * Deterministic except for voxels that hold several targets.  Synchronises
+ * the stream.  Errors: EINVAL, EDEVICE. */
+int bemfft_net_gradients(bemfft_net *n, const float *x, int64_t nt, const int *vox, const float *tgt,
+                         const float *wt, double *loss, float *grad_host, void *stream);
+
+/* One Adam step (learning rate lr) on the loss above; the loss before the
+ * step goes to *loss.  Synchronises the stream. */
+int bemfft_net_train_step(bemfft_net *n, const float *x, int64_t nt, const int *vox, const float *tgt,
+                          const float *wt, float lr, double *loss, void *stream);
+
+/* Initial guess for bemfft_solve: x0 device [m] doubles, q_j at Dirichlet
+ * slots, 0 elsewhere; xbuf device [6][n^3] floats is scratch; s is taken
+ * from 'known' (one host round trip).  Errors: as bemfft_net_input. */
+int bemfft_net_guess(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const double *known,
+                     float *xbuf, double *x0, void *stream);
+
+/* Voxel index (z*n*n + y*n + x) and weight w_j of each node, in the
+ * caller's node order (host arrays of m; either may be NULL). */
+int bemfft_plan_node_voxels(const bemfft_plan *p, int *vox_host, double *w_host);
 
 /* In-place FP64 complex 3D FFT of a device array [pz][py][px] of interleaved
  * (re, im) doubles with the library's own transform kernels (the transform

@@ -41,7 +41,7 @@ class bemfft_solve_opts(ctypes.Structure):
 class bemfft_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("true_relres", ctypes.c_double),
                 ("status", ctypes.c_int), ("seconds", ctypes.c_double), ("outer", ctypes.c_int),
-                ("applies64", ctypes.c_int)]
+                ("applies64", ctypes.c_int), ("x0_used", ctypes.c_int), ("x0_relres", ctypes.c_double)]
 
 
 class bemfft_plan_info(ctypes.Structure):
@@ -58,7 +58,10 @@ EXPORTS = [
     "bemfft_plan_create", "bemfft_apply", "bemfft_apply_profile", "bemfft_solve", "bemfft_plan_get_info", "bemfft_plan_get_c",
     "bemfft_plan_destroy", "bemfft_fft3d_c2c_f64", "bemfft_strerror", "bemfft_last_error",
     "bemfft_supported_sizes", "bemfft_batch_create", "bemfft_batch_apply", "bemfft_batch_solve",
-    "bemfft_batch_members", "bemfft_batch_destroy",
+    "bemfft_batch_members", "bemfft_batch_destroy", "bemfft_net_create", "bemfft_net_destroy",
+    "bemfft_net_num_params", "bemfft_net_get_params", "bemfft_net_set_params", "bemfft_net_input",
+    "bemfft_net_forward", "bemfft_net_gradients", "bemfft_net_train_step", "bemfft_net_guess",
+    "bemfft_plan_node_voxels",
 ]
 
 _lib = None
@@ -101,6 +104,20 @@ def load():
                                      ctypes.POINTER(bemfft_solve_info), vp]
     L.bemfft_batch_members.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.bemfft_batch_destroy.argtypes = [vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.bemfft_net_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.c_uint64, vp]
+    L.bemfft_net_destroy.argtypes = [vp]
+    L.bemfft_net_num_params.argtypes = [vp]
+    L.bemfft_net_num_params.restype = i64
+    L.bemfft_net_get_params.argtypes = [vp, fp]
+    L.bemfft_net_set_params.argtypes = [vp, fp]
+    L.bemfft_net_input.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.bemfft_net_forward.argtypes = [vp, vp, vp, vp]
+    L.bemfft_net_gradients.argtypes = [vp, vp, i64, vp, vp, vp, dp, fp, vp]
+    L.bemfft_net_train_step.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_float, dp, vp]
+    L.bemfft_net_guess.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.bemfft_plan_node_voxels.argtypes = [vp, ctypes.POINTER(ctypes.c_int), dp]
     _lib = L
     return L
 
@@ -196,7 +213,8 @@ def bemfft_solve(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, pr
                              _stream_ptr(stream))
     _check(st, "bemfft_solve")
     return {"status": st, "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
-            "seconds": info.seconds, "outer": info.outer, "applies64": info.applies64}
+            "seconds": info.seconds, "outer": info.outer, "applies64": info.applies64,
+            "x0_used": info.x0_used, "x0_relres": info.x0_relres}
 
 
 def bemfft_plan_get_info(plan):
@@ -311,6 +329,84 @@ class Batch:
     def close(self):
         if self.handle is not None and self.handle.value:
             load().bemfft_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_node_voxels(plan, m):
+    """(voxel index int32[m], weight float64[m]) of each node, caller's order."""
+    vox = np.zeros(m, dtype=np.int32)
+    w = np.zeros(m)
+    _check(load().bemfft_plan_node_voxels(plan, vox.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                          w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "bemfft_plan_node_voxels")
+    return vox, w
+
+
+class Net:
+    """The learned-start network (bemfft_net_* in include/bemfft.h)."""
+
+    def __init__(self, grid, dilations=(1, 2, 4, 8), width=16, seed=0, stream=None):
+        self.grid = int(grid)
+        self.dilations = list(dilations)
+        dil = (ctypes.c_int * len(self.dilations))(*self.dilations)
+        self.handle = ctypes.c_void_p()
+        _check(load().bemfft_net_create(ctypes.byref(self.handle), self.grid, int(width), len(self.dilations), dil,
+                                        ctypes.c_uint64(seed), _stream_ptr(stream) if stream is not None else None),
+               "bemfft_net_create")
+        self.nparam = int(load().bemfft_net_num_params(self.handle))
+        self.V = self.grid ** 3
+
+    def params(self):
+        buf = np.zeros(self.nparam, dtype=np.float32)
+        _check(load().bemfft_net_get_params(self.handle, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "bemfft_net_get_params")
+        return buf
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        if params.shape != (self.nparam,):
+            raise ValueError(f"expected {self.nparam} parameters")
+        _check(load().bemfft_net_set_params(self.handle, params.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "bemfft_net_set_params")
+
+    def input(self, plan, bc, known, scale, x, stream=None):
+        _check(load().bemfft_net_input(self.handle, plan.handle, _ptr(bc) if bc is not None else None, _ptr(known),
+                                       float(scale), _ptr(x), _stream_ptr(stream)), "bemfft_net_input")
+        return x
+
+    def forward(self, x, y, stream=None):
+        _check(load().bemfft_net_forward(self.handle, _ptr(x), _ptr(y), _stream_ptr(stream)), "bemfft_net_forward")
+        return y
+
+    def gradients(self, x, vox, tgt, wt, stream=None):
+        loss = ctypes.c_double()
+        g = np.zeros(self.nparam, dtype=np.float32)
+        _check(load().bemfft_net_gradients(self.handle, _ptr(x), int(vox.numel()), _ptr(vox), _ptr(tgt), _ptr(wt),
+                                           ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                           _stream_ptr(stream)), "bemfft_net_gradients")
+        return loss.value, g
+
+    def train_step(self, x, vox, tgt, wt, lr, stream=None):
+        loss = ctypes.c_double()
+        _check(load().bemfft_net_train_step(self.handle, _ptr(x), int(vox.numel()), _ptr(vox), _ptr(tgt), _ptr(wt),
+                                            float(lr), ctypes.byref(loss), _stream_ptr(stream)),
+               "bemfft_net_train_step")
+        return loss.value
+
+    def guess(self, plan, bc, known, xbuf, x0, stream=None):
+        _check(load().bemfft_net_guess(self.handle, plan.handle, _ptr(bc) if bc is not None else None, _ptr(known),
+                                       _ptr(xbuf), _ptr(x0), _stream_ptr(stream)), "bemfft_net_guess")
+        return x0
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            load().bemfft_net_destroy(self.handle)
         self.handle = None
 
     def __del__(self):

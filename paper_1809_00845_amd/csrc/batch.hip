@@ -436,8 +436,9 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
     }
     bemfft_solve_opts o{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
     if (opts) o = *opts;
-    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.refine) {
-        set_error("batch_solve: bad options (refine is not supported for batches)");
+    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.refine || o.use_x0 < 0 ||
+        o.use_x0 > 1) {
+        set_error("batch_solve: bad options (refine and use_x0 = 2 are not supported for batches)");
         return BEMFFT_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -651,6 +652,8 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
             info[k].seconds = secs;
             info[k].outer = 0;
             info[k].applies64 = 0;
+            info[k].x0_used = o.use_x0 ? 1 : 0;
+            info[k].x0_relres = -1.0;
         }
     }
     return status;

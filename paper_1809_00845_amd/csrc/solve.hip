@@ -334,7 +334,7 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
     }
     bemfft_solve_opts o{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
     if (opts) o = *opts;
-    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1) {
+    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.use_x0 < 0 || o.use_x0 > 2) {
         set_error("solve: bad options");
         return BEMFFT_EINVAL;
     }
@@ -367,9 +367,26 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
     if (o.use_x0) BF_HIP(hipMemcpyAsync(ws.x, unknown, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     else BF_HIP(hipMemsetAsync(ws.x, 0, n * sizeof(double), st));
     int iters = 0, restarts = 0, outer = 0, applies64 = 1;
-    double rel = 0.0;
+    double rel = 0.0, rel0 = 1.0;
+    bool use_x0 = o.use_x0 != 0;
+    if (o.use_x0 == 2) {
+        // keep the guess only if its true residual is below that of x = 0
+        int s2 = 0;
+        BF_CHECK(apply_unknown(p, eo, bc, ws.x, nullptr, ws, ws.ro, st));
+        hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.ro, ws.b, 1.0, -1.0, n);
+        BF_HIP(hipGetLastError());
+        const double rn = norm2(ws.ro, n, ws, hp, st, &s2);
+        BF_CHECK(s2);
+        const double bn = norm2(ws.b, n, ws, hp, st, &s2);
+        BF_CHECK(s2);
+        rel0 = bn > 0.0 ? rn / bn : 0.0;
+        if (!(rn < bn)) {
+            use_x0 = false;
+            BF_HIP(hipMemsetAsync(ws.x, 0, n * sizeof(double), st));
+        }
+    }
     if (!o.refine) {
-        status = gmres_core(p, p->eng, bc, ws.b, ws.x, !o.use_x0, o.tol, o.restart, o.maxit, ws, hp, st, &iters,
+        status = gmres_core(p, p->eng, bc, ws.b, ws.x, !use_x0, o.tol, o.restart, o.maxit, ws, hp, st, &iters,
                             &restarts, &rel);
     } else {
         // iterative refinement: r = b - A64 x in FP64, d ~ A^-1 r in the
@@ -377,7 +394,7 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
         int st2 = 0;
         const double bnorm = norm2(ws.b, n, ws, hp, st, &st2);
         BF_CHECK(st2);
-        bool x_zero = !o.use_x0;
+        bool x_zero = !use_x0;
         for (;;) {
             if (x_zero) {
                 BF_HIP(hipMemcpyAsync(ws.ro, ws.b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -422,6 +439,8 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->outer = outer;
         info->applies64 = o.refine ? applies64 : 0;
+        info->x0_used = use_x0 ? 1 : 0;
+        info->x0_relres = o.use_x0 == 2 ? rel0 : -1.0;
     }
     return status;
 }

@@ -87,3 +87,11 @@ def test_null_arguments(lib):
     assert lib.bemfft_solve(None, None, None, None, None, None, None) == B.EINVAL
     assert lib.bemfft_plan_destroy(None) == 0
     assert lib.bemfft_plan_get_info(None, None) == B.EINVAL
+
+
+def test_net_validation_rejects_before_device_work(lib):
+    for grid, layers, dil in [(2, 4, (1, 2, 4, 8)), (300, 4, (1, 2, 4, 8)), (16, 1, (1,)), (16, 2, (1, 0)),
+                              (16, 2, (1, 17))]:
+        with pytest.raises(B.BemfftError) as ei:
+            B.Net(grid, dil[:layers])
+        assert ei.value.status == B.EINVAL
