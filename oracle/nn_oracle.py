@@ -9,7 +9,10 @@ q sought) to a guess of q for the iterative solve.  Everything here is
 written from the definitions, in numpy FP64:
 
 * input channels on the n^3 grid, summed over the nodes of each voxel:
-  a = w/h^2, a*n_x, a*n_y, a*n_z, a*s*u (s = 1/rms(u) over Dirichlet slots);
+  a = w/h^2, a*n_x, a*n_y, a*n_z, a*s*u, a*s*b (u the Dirichlet data,
+  s = 1/rms(u) over Dirichlet slots, b the right-hand side of the solve:
+  minus the operator applied to the known values, eq. 4 with the unknowns
+  set to zero);
 * output y at the voxel of node j approximates s*h*q_j (a flux per voxel
   length, O(1) for smooth data), so the guess is q_j = y / (s h);
 * layers: 3x3x3 cross-correlation with dilation d and zero padding,
@@ -29,12 +32,15 @@ import numpy as np
 OFFSETS = [(oz, oy, ox) for oz in (-1, 0, 1) for oy in (-1, 0, 1) for ox in (-1, 0, 1)]
 
 
-def layer_shapes(layers: int, cin: int = 5, width: int = 16):
+CIN = 6
+
+
+def layer_shapes(layers: int, cin: int = CIN, width: int = 16):
     """(cin, cout) of every layer: cin -> width -> ... -> width -> 1."""
     return [(cin if l == 0 else width, 1 if l == layers - 1 else width) for l in range(layers)]
 
 
-def unpack(params, layers: int, cin: int = 5, width: int = 16):
+def unpack(params, layers: int, cin: int = CIN, width: int = 16):
     """Split the flat parameter vector into [(W[cout, cin, 27], b[cout])]."""
     out, k = [], 0
     for ci, co in layer_shapes(layers, cin, width):
@@ -52,14 +58,15 @@ def pack(layer_params):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layer_params])
 
 
-def channels(grid_index, G: int, h: float, weights, normals, u, bc, s: float):
-    """Input channels [5, G, G, G] of a problem (nodes snapped to grid_index,
+def channels(grid_index, G: int, h: float, weights, normals, u, b, bc, s: float):
+    """Input channels [6, G, G, G] of a problem (nodes snapped to grid_index,
     [m, 3] as (ix, iy, iz)); bc = None means every slot is Dirichlet."""
-    x = np.zeros((5, G, G, G))
+    x = np.zeros((CIN, G, G, G))
     a = np.asarray(weights, dtype=np.float64) / (h * h)
     dir_ = np.ones(len(a), dtype=bool) if bc is None else (np.asarray(bc) == 0)
     uu = np.where(dir_, np.asarray(u, dtype=np.float64), 0.0)
-    vals = [a, a * normals[:, 0], a * normals[:, 1], a * normals[:, 2], a * s * uu]
+    vals = [a, a * normals[:, 0], a * normals[:, 1], a * normals[:, 2], a * s * uu,
+            a * s * np.asarray(b, dtype=np.float64)]
     ix, iy, iz = grid_index[:, 0], grid_index[:, 1], grid_index[:, 2]
     for c, v in enumerate(vals):
         np.add.at(x[c], (iz, iy, ix), v)
@@ -108,7 +115,7 @@ def conv_weight_grad(g, x, d: int):
     return gW, g.sum(axis=(1, 2, 3))
 
 
-def forward(params, dilations, x, cin: int = 5, width: int = 16):
+def forward(params, dilations, x, cin: int = CIN, width: int = 16):
     """Returns (y [G,G,G], list of layer inputs, list of pre-activations)."""
     lp = unpack(params, len(dilations), cin, width)
     inputs, pres = [], []
@@ -121,7 +128,7 @@ def forward(params, dilations, x, cin: int = 5, width: int = 16):
     return a[0], inputs, pres
 
 
-def loss_and_grad(params, dilations, x, vox, tgt, wt, cin: int = 5, width: int = 16):
+def loss_and_grad(params, dilations, x, vox, tgt, wt, cin: int = CIN, width: int = 16):
     """L = sum_i wt_i (y.flat[vox_i] - tgt_i)^2 and dL/dparams (flat)."""
     lp = unpack(params, len(dilations), cin, width)
     y, inputs, pres = forward(params, dilations, x, cin, width)

@@ -15,7 +15,7 @@ from oracle import nn_oracle as nn
 DIL = [1, 2, 4]
 
 
-def _params(rng, layers, cin=5, width=16, scale=0.3):
+def _params(rng, layers, cin=nn.CIN, width=16, scale=0.3):
     lp = [(scale * rng.standard_normal((co, ci, 27)), scale * rng.standard_normal(co))
           for ci, co in nn.layer_shapes(layers, cin, width)]
     return nn.pack(lp)
@@ -68,7 +68,7 @@ def test_conv_transpose_is_adjoint():
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
 
 
-def _problem(rng, G=7, nt=40, cin=5):
+def _problem(rng, G=7, nt=40, cin=nn.CIN):
     x = np.zeros((cin, G, G, G))
     vox = rng.choice(G ** 3, size=nt, replace=False)
     for c in range(cin):
@@ -85,7 +85,7 @@ def test_gradient_finite_differences():
     L, g = nn.loss_and_grad(p, DIL, x, vox, tgt, wt)
     idx = rng.choice(len(p), size=30, replace=False)
     # the bias and the last layer are always touched
-    idx = np.concatenate([idx, [len(p) - 1, len(p) - 2, 16 * 5 * 27]])
+    idx = np.concatenate([idx, [len(p) - 1, len(p) - 2, 16 * nn.CIN * 27]])
     eps = 1e-6
     for i in idx:
         pp, pm = p.copy(), p.copy()
@@ -165,7 +165,8 @@ def test_channels_sums():
     g = inputs.sphere3d(24, 0.35)
     idx = oracle.snap(oracle.problem(g, oracle.LAPLACE3D))
     u = np.ones(g.m)
-    x = nn.channels(idx, 24, g.h, g.weights, g.normals, u, None, 1.0)
+    b = np.full(g.m, 2.0)
+    x = nn.channels(idx, 24, g.h, g.weights, g.normals, u, b, None, 1.0)
     a_sum = g.weights.sum() / g.h ** 2
     # total area in voxel units, and a closed surface has zero mean normal
     assert abs(x[0].sum() - a_sum) <= 1e-12 * a_sum
@@ -173,6 +174,7 @@ def test_channels_sums():
         assert abs(x[c].sum()) <= 1e-2 * a_sum
     # u = 1, s = 1: the data channel equals the area channel
     np.testing.assert_allclose(x[4], x[0], rtol=0, atol=1e-12)
-    # Neumann slots carry no data
+    np.testing.assert_allclose(x[5], 2.0 * x[0], rtol=0, atol=1e-12)
+    # Neumann slots carry no Dirichlet data
     bc = np.ones(g.m, dtype=np.uint8)
-    assert np.abs(nn.channels(idx, 24, g.h, g.weights, g.normals, u, bc, 1.0)[4]).max() == 0.0
+    assert np.abs(nn.channels(idx, 24, g.h, g.weights, g.normals, u, b, bc, 1.0)[4]).max() == 0.0
