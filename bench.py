@@ -51,19 +51,15 @@ def stage_bytes(info, prec_bytes):
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of 'kernel' from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
-    calibration factor), or None when the kernel sources have changed since
-    the counters were taken."""
-    import hashlib
+    calibration factor), or None when the sources of the apply kernels have
+    changed since the counters were taken."""
+    from paper_1809_00845_amd.profile_summary import apply_sources_sha256
 
     path = os.path.join(ROOT, "profiles", "apply_laplace3d_cube128_fp32_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    csrc = os.path.join(ROOT, "paper_1809_00845_amd", "csrc")
-    h = hashlib.sha256()
-    for fn in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, fn), "rb").read())
-    if rec.get("workload") != workload or rec.get("csrc_sha256") != h.hexdigest():
+    if rec.get("workload") != workload or rec.get("csrc_sha256") != apply_sources_sha256():
         return None
     k = rec["kernels"].get("k_" + kernel)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
@@ -201,6 +197,48 @@ def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
     return out
 
 
+def bench_navier_star(B, I, dev, steps):
+    """Navier (Kelvin, nu = 0.3, mu = 1) on the star surface of seed 1 on a
+    192^3 grid padded to 384^3: FP32 / FP64 applies and time to solve for the
+    traction under a given linear displacement field, to 1e-6."""
+    import torch
+
+    t0 = time.perf_counter()
+    g = I.star3d(192, I.draw_stars(1, 1)[0])
+    t_geom = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    q = torch.tensor(rng.uniform(-1, 1, (3, g.m)), device=dev)
+    u = torch.tensor(rng.uniform(-1, 1, (3, g.m)), device=dev)
+    r = torch.empty_like(u)
+    out = {"nodes": g.m, "grid": 192, "pad": 384, "voxelise_s": t_geom}
+    p32 = B.Plan(g, B.NAVIER3D, precision=B.FP32, nu=0.3, mu=1.0, keep_fp64=True, autotune=1)
+    p64 = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=0.3, mu=1.0)
+    n32, n64 = max(20, steps // 4), max(10, steps // 10)
+    out["fp32_matvec_s"] = n32 / timed_applies(p32, q, u, r, n32, 5)
+    out["fp64_matvec_s"] = n64 / timed_applies(p64, q, u, r, n64, 3)
+    names = ["fwd_xy", "zpass", "inv_yx", "epilogue"]
+    out["fp32_stage_ms"] = dict(zip(names, B.bemfft_apply_profile(p32.handle, q, u, r, reps=20)))
+    out["plan_seconds"] = {"fp32_keep_fp64": p32.info()["plan_seconds"], "fp64": p64.info()["plan_seconds"]}
+    E = np.random.default_rng(11).normal(size=(3, 3))
+    uu = (g.rel() @ E.T).T
+    bct = torch.zeros((3, g.m), dtype=torch.uint8, device=dev)
+    known = torch.tensor(uu, device=dev)
+    solves = {}
+    for tag, pl, kw in (("fp64", p64, {}), ("fp32", p32, {}), ("fp32_refined_fp64", p32, {"refine": 1, "inner_tol": 1e-3})):
+        pl.solve(bct, known, tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, si = pl.solve(bct, known, tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        solves[tag] = {"seconds": time.perf_counter() - t0, "iters": si["iters"], "outer": si["outer"],
+                       "true_relres": si["true_relres"], "status": si["status"],
+                       "residual_precision": "fp32" if tag == "fp32" else "fp64"}
+    out["time_to_solve_1e-6"] = solves
+    p32.close()
+    p64.close()
+    return out
+
+
 def bench_learned(B, args):
     """Learned start: a 4-layer, 16-channel dilated conv net on the G^3 grid,
     trained on the GPU with the library's kernels on star problems (seed 3)
@@ -246,6 +284,14 @@ def bench_learned(B, args):
         net.forward(xb, yb)
     torch.cuda.synchronize()
     t_fwd = (time.perf_counter() - t0) / 20
+    for _ in range(3):
+        net.infer(xb, yb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        net.infer(xb, yb)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / 50
     t0 = time.perf_counter()
     rows = LS.evaluate(net, probs[ntr:])
     t_eval = time.perf_counter() - t0
@@ -254,13 +300,15 @@ def bench_learned(B, args):
     return {
         "workload": f"learned start: star surfaces (seed 3) on {G}^3, pad {2 * G}^3, Laplace Dirichlet, "
                     f"{ntr} train / {nte} held-out, GMRES(100) right Jacobi to 1e-6, FP64",
-        "network": "conv3d 3x3x3 dilations 1,2,4,8; 6->16->16->16->1; ReLU; FP32",
+        "network": "conv3d 3x3x3 dilations 1,2,4,8; 6->16->16->16->1; ReLU; trained in FP32, "
+                   "inference FP16 on the matrix cores with FP32 accumulation",
         "params": net.nparam,
         "epochs": args.learned_epochs,
         "test_rel_sq_error_before": e0, "test_rel_sq_error_after": e1,
         "train_loss_per_epoch": hist,
         "ms_per_train_step": 1e3 * t_grad,
-        "ms_per_forward": 1e3 * t_fwd,
+        "ms_per_forward_fp32": 1e3 * t_fwd,
+        "ms_per_inference_fp16_mfma": 1e3 * t_inf,
         "seconds": {"voxelise": t_geom, "solve_and_inputs": t_data, "train": t_train, "evaluate": t_eval},
         **sm,
     }
@@ -275,6 +323,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="apply timing only (for profilers)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-shape batched workload")
     ap.add_argument("--batched-only", action="store_true", help="only the 64-shape batched workload")
+    ap.add_argument("--no-navier", action="store_true", help="skip the 192^3 Navier star workload")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only the mixed cube solves to 1e-6 (FP64 and FP32 plans), 3 each (for profilers)")
     ap.add_argument("--learned", action="store_true",
                     help="only the learned-start workload: train on GPU-solved star problems, then compare solves")
     ap.add_argument("--learned-grid", type=int, default=96)
@@ -310,6 +361,26 @@ def main():
         return
     if args.learned:
         print(json.dumps(bench_learned(B, args)), flush=True)
+        return
+    if args.solve_only:
+        g = I.cube3d(128, 100)
+        uu, qq = I.harmonic_3d_xyz(g)
+        bc = I.mixed_bc_upper(g)
+        known = torch.tensor(np.where(bc == 0, uu, qq), device=dev)
+        bct = torch.tensor(bc, device=dev)
+        res = {}
+        for tag, prec in (("fp64", B.FP64), ("fp32", B.FP32)):
+            pl = B.Plan(g, B.LAPLACE3D, precision=prec)
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, si = pl.solve(bct, known, tol=1e-6)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[tag] = {"seconds": ts, "iters": si["iters"], "true_relres": si["true_relres"]}
+            pl.close()
+        print(json.dumps({"workload": "laplace3d cube 128^3 mixed solve to 1e-6", **res}), flush=True)
         return
     cube = I.cube3d(128, 100)
     uh, qh = I.harmonic_3d_xyz(cube)
@@ -393,6 +464,9 @@ def main():
                                            "status": si["status"]}
         extra["time_to_solve_1e-6"] = solves
         extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
+        if not args.no_navier:
+            print("  navier star 192^3 ...", file=sys.stderr, flush=True)
+            extra["navier_star_192"] = bench_navier_star(B, I, dev, args.steps)
         if not args.no_batched:
             plan64.close()
             extra["batched_64_stars_4rhs"] = bench_batched(B, I, dev)

@@ -291,8 +291,15 @@ int bemfft_net_set_params(bemfft_net *n, const float *params_host);
 int bemfft_net_input(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const double *known,
                      double scale, float *x, void *stream);
 
-/* y device [n^3] = network(x). */
+/* y device [n^3] = network(x), FP32 storage and arithmetic (the training
+ * path). */
 int bemfft_net_forward(bemfft_net *n, const float *x, float *y, void *stream);
+
+/* y device [n^3] = network(x) for inference: activations and weights in
+ * FP16 (channel-last), products on the matrix cores with FP32 accumulation,
+ * bias and ReLU in FP32 before the FP16 rounding; y is FP32.  Used by
+ * bemfft_net_guess.  Relative error against the FP32 path ~1e-3. */
+int bemfft_net_infer(bemfft_net *n, const float *x, float *y, void *stream);
 
 /* Loss sum_i wt_i (y(vox_i) - tgt_i)^2 of input x (all device arrays, nt
  * targets, vox = z*n*n + y*n + x) and its gradient with respect to every
@@ -308,8 +315,10 @@ int bemfft_net_train_step(bemfft_net *n, const float *x, int64_t nt, const int *
                           const float *wt, float lr, double *loss, void *stream);
 
 /* Initial guess for bemfft_solve: x0 device [m] doubles, q_j at Dirichlet
- * slots, 0 elsewhere; xbuf device [6][n^3] floats is scratch; s is taken
- * from 'known' (one host round trip).  Errors: as bemfft_net_input. */
+ * slots, 0 elsewhere; xbuf device [6][n^3] floats is scratch.  s is computed
+ * on the device; one apply of the plan, the FP16 inference and the gather
+ * are queued on 'stream' (no host synchronisation).  Errors: as
+ * bemfft_net_input. */
 int bemfft_net_guess(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const double *known,
                      float *xbuf, double *x0, void *stream);
 

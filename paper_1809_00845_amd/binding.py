@@ -60,7 +60,7 @@ EXPORTS = [
     "bemfft_supported_sizes", "bemfft_batch_create", "bemfft_batch_apply", "bemfft_batch_solve",
     "bemfft_batch_members", "bemfft_batch_destroy", "bemfft_net_create", "bemfft_net_destroy",
     "bemfft_net_num_params", "bemfft_net_get_params", "bemfft_net_set_params", "bemfft_net_input",
-    "bemfft_net_forward", "bemfft_net_gradients", "bemfft_net_train_step", "bemfft_net_guess",
+    "bemfft_net_forward", "bemfft_net_infer", "bemfft_net_gradients", "bemfft_net_train_step", "bemfft_net_guess",
     "bemfft_plan_node_voxels",
 ]
 
@@ -114,6 +114,7 @@ def load():
     L.bemfft_net_set_params.argtypes = [vp, fp]
     L.bemfft_net_input.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
     L.bemfft_net_forward.argtypes = [vp, vp, vp, vp]
+    L.bemfft_net_infer.argtypes = [vp, vp, vp, vp]
     L.bemfft_net_gradients.argtypes = [vp, vp, i64, vp, vp, vp, dp, fp, vp]
     L.bemfft_net_train_step.argtypes = [vp, vp, i64, vp, vp, vp, ctypes.c_float, dp, vp]
     L.bemfft_net_guess.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -382,6 +383,10 @@ class Net:
 
     def forward(self, x, y, stream=None):
         _check(load().bemfft_net_forward(self.handle, _ptr(x), _ptr(y), _stream_ptr(stream)), "bemfft_net_forward")
+        return y
+
+    def infer(self, x, y, stream=None):
+        _check(load().bemfft_net_infer(self.handle, _ptr(x), _ptr(y), _stream_ptr(stream)), "bemfft_net_infer")
         return y
 
     def gradients(self, x, vox, tgt, wt, stream=None):

@@ -155,15 +155,17 @@ __global__ __launch_bounds__(256) void kbs_mdot_partial(const double *V, const i
 }
 
 // hb[k * kHs + base + j] = sum_blk partial[k][blk][j] (sqrt if sqrt_out)
-__global__ void kbs_mdot_final(const double *partial, int nblk, int nvec, double *hb, int base, int sqrt_out,
-                               const int *active) {
-    const int k = blockIdx.x;
+// hb[k][base + j] = sum over blocks of partial[k][b][j]: one wavefront per
+// (member, j), fixed-order lane sums and shuffle tree (deterministic)
+__global__ __launch_bounds__(64) void kbs_mdot_final(const double *partial, int nblk, int nvec, double *hb, int base,
+                                                     int sqrt_out, const int *active) {
+    const int k = blockIdx.x, j = blockIdx.y;
     if (!active[k]) return;
-    for (int j = threadIdx.x; j < nvec; j += blockDim.x) {
-        double s = 0.0;
-        for (int bl = 0; bl < nblk; ++bl) s += partial[((int64_t)k * nblk + bl) * nvec + j];
-        hb[(int64_t)k * kHs + base + j] = sqrt_out ? sqrt(s) : s;
-    }
+    double s = 0.0;
+    for (int bl = threadIdx.x; bl < nblk; bl += 64) s += partial[((int64_t)k * nblk + bl) * nvec + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) hb[(int64_t)k * kHs + base + j] = sqrt_out ? sqrt(s) : s;
 }
 
 // w_k += sign * V_k h_k, h_k = hb[k * kHs + base ...]
@@ -477,7 +479,7 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
     auto norms = [&](const double *vec, std::vector<double> &outn) -> int {
         hipLaunchKernelGGL(kbs_mdot_partial, dim3(kBpm, nm), dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len, 1,
                            vec, b->s_red, b->d_active, 1);
-        hipLaunchKernelGGL(kbs_mdot_final, dim3(nm), dim3(64), 0, st, b->s_red, kBpm, 1, b->s_hb, 512, 1, b->d_active);
+        hipLaunchKernelGGL(kbs_mdot_final, dim3(nm, 1), dim3(64), 0, st, b->s_red, kBpm, 1, b->s_hb, 512, 1, b->d_active);
         hipLaunchKernelGGL(kbs_combine, dim3(nm), dim3(64), 0, st, b->s_hb, -1, b->s_hc, 512, b->d_active);
         BF_HIP(hipGetLastError());
         BF_HIP(hipMemcpy2DAsync(b->h_hc, sizeof(double), b->s_hc, 512 * sizeof(double), sizeof(double), nm,
@@ -560,14 +562,14 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
                 const int base = pass * 512;
                 hipLaunchKernelGGL(kbs_mdot_partial, dim3(kBpm, nm), dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len,
                                    it + 1, w, b->s_red, b->d_active, 0);
-                hipLaunchKernelGGL(kbs_mdot_final, dim3(nm), dim3(64), 0, st, b->s_red, kBpm, it + 1, b->s_hb, base, 0,
+                hipLaunchKernelGGL(kbs_mdot_final, dim3(nm, it + 1), dim3(64), 0, st, b->s_red, kBpm, it + 1, b->s_hb, base, 0,
                                    b->d_active);
                 hipLaunchKernelGGL(kbs_gemv, gm, dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len, it + 1, b->s_hb,
                                    base, w, -1.0, b->d_active);
             }
             hipLaunchKernelGGL(kbs_mdot_partial, dim3(kBpm, nm), dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len, 1,
                                w, b->s_red, b->d_active, 1);
-            hipLaunchKernelGGL(kbs_mdot_final, dim3(nm), dim3(64), 0, st, b->s_red, kBpm, 1, b->s_hb, 512 + it + 1, 1,
+            hipLaunchKernelGGL(kbs_mdot_final, dim3(nm, 1), dim3(64), 0, st, b->s_red, kBpm, 1, b->s_hb, 512 + it + 1, 1,
                                b->d_active);
             hipLaunchKernelGGL(kbs_normalize, gm, dim3(256), 0, st, w, b->s_hb, 512 + it + 1, V, b->d_voff, b->d_off,
                                b->d_len, it + 1, b->d_active);

@@ -13,6 +13,7 @@
 // residual is smaller than ||b|| (plain GMRES from zero otherwise).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <random>
@@ -35,6 +36,13 @@ struct bemfft_net {
     int64_t t = 0;                          // Adam step
     double *dq = nullptr, *du = nullptr, *db = nullptr;  // right-hand side scratch [cap]
     int64_t cap = 0;
+    // inference in FP16: channel-last activations [V][16] (ping-pong), packed
+    // weights [layer][27][16][16], biases [layer][16], scale s on the device
+    _Float16 *ha = nullptr, *hb = nullptr, *wp = nullptr;
+    float *bp = nullptr;
+    double *sdev = nullptr;
+    int64_t *d_woff = nullptr, *d_boff = nullptr;
+    int *d_ci = nullptr, *d_co = nullptr;
 };
 
 namespace bemfft {
@@ -71,9 +79,10 @@ __global__ void k_nn_split(const uint8_t *bc, const double *known, double *q, do
 // voxel add up; atomics keep that correct whatever the node order.
 __global__ void k_nn_input(const int *gx, const int *gy, const int *gz, const int *perm, const double *w,
                            const double *nrm, const double *known, const double *r, const uint8_t *bc, int64_t m,
-                           int G, double inv_h2, double s, float *x, int64_t V) {
+                           int G, double inv_h2, double s_host, const double *s_dev, float *x, int64_t V) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= m) return;
+    const double s = s_dev ? *s_dev : s_host;
     const int j = perm[k];
     const int64_t v = ((int64_t)gz[k] * G + gy[k]) * G + gx[k];
     const double ww = w[k] * inv_h2;
@@ -268,12 +277,129 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, 
 
 // x0 at the Dirichlet slots: y(v_j) / (s h)
 __global__ void k_nn_gather(const float *y, const int *gx, const int *gy, const int *gz, const int *perm,
-                            const uint8_t *bc, int64_t m, int G, double inv_s, double *x0) {
+                            const uint8_t *bc, int64_t m, int G, const double *s_dev, double h, double *x0) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= m) return;
     const int j = perm[k];
     const int64_t v = ((int64_t)gz[k] * G + gy[k]) * G + gx[k];
-    x0[j] = (bc == nullptr || bc[j] == 0) ? (double)y[v] * inv_s : 0.0;
+    x0[j] = (bc == nullptr || bc[j] == 0) ? (double)y[v] / (*s_dev * h) : 0.0;
+}
+
+// s = 1/rms(u) over the Dirichlet slots (1 if there are none or u = 0):
+// one block, fixed-order reduction
+__global__ __launch_bounds__(256) void k_nn_scale(const double *known, const uint8_t *bc, int64_t m, double *s_out) {
+    __shared__ double ss[256], sc[256];
+    double a = 0.0, c = 0.0;
+    for (int64_t j = threadIdx.x; j < m; j += 256)
+        if (bc == nullptr || bc[j] == 0) {
+            a += known[j] * known[j];
+            c += 1.0;
+        }
+    ss[threadIdx.x] = a;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ss[threadIdx.x] += ss[threadIdx.x + o];
+            sc[threadIdx.x] += sc[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *s_out = (ss[0] > 0.0 && sc[0] > 0.0) ? 1.0 / sqrt(ss[0] / sc[0]) : 1.0;
+}
+
+// ---------------------------------------------------------------- FP16 inference
+// Implicit-GEMM convolution on the matrix cores: for each tap t, the 16 x 16
+// weight block W[c][ci][t] (rows c) times the 16 x 16 block of activations
+// act[v_j + d o_t][ci] of 16 consecutive voxels (columns j), accumulated in
+// FP32 over the 27 taps.  Activations are FP16, channel-last [V][16], so one
+// lane's four B values are one 8-byte load.  Operand layout of the 16x16x16
+// MFMA (wave of 64): A[i][k] at lane i + 16 (k / 4), element k % 4; B[k][j] at
+// lane j + 16 (k / 4), element k % 4; D[i][j] at lane j + 16 (i / 4),
+// element i % 4.
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// planar FP32 [cin][V] -> channel-last FP16 [V][16], channels >= cin zero
+__global__ void k_to_cl16(const float *x, int cin, int64_t V, _Float16 *o) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    h4 w[4];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) w[c / 4][c % 4] = (_Float16)(c < cin ? x[(int64_t)c * V + v] : 0.f);
+    h4 *dst = reinterpret_cast<h4 *>(o + v * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = w[q];
+}
+
+// FP32 parameters W[co][ci][27], b[co] of every layer -> FP16 Wp[l][27][16][16]
+// (zero-padded to 16 x 16) and FP32 bp[l][16]
+__global__ void k_pack16(const float *p, const int64_t *woff, const int64_t *boff, const int *ci, const int *co,
+                         _Float16 *wp, float *bp) {
+    const int l = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // t*256 + c*16 + k
+    if (i >= 27 * 256) return;
+    const int t = i / 256, c = (i / 16) % 16, k = i % 16;
+    const float w = (c < co[l] && k < ci[l]) ? p[woff[l] + ((int64_t)c * ci[l] + k) * 27 + t] : 0.f;
+    wp[(int64_t)l * 27 * 256 + i] = (_Float16)w;
+    if (i < 16) bp[l * 16 + i] = i < co[l] ? p[boff[l] + i] : 0.f;
+}
+
+// Tiles of 16 consecutive voxels; each wave keeps its 27 weight blocks in
+// registers and walks many tiles.  Blocks are mapped so that the 8 XCDs
+// (blocks go round-robin to them) each sweep one contiguous range of tiles:
+// the dilated taps then re-read planes that the same XCD's L2 just fetched.
+// Three accumulators (one per dz) keep three independent MFMA chains.
+template <bool LAST>
+__global__ __launch_bounds__(256) void k_conv16(const _Float16 *__restrict__ in, const _Float16 *__restrict__ Wp,
+                                                const float *__restrict__ bias, _Float16 *__restrict__ out,
+                                                float *__restrict__ y, int G, int d, int64_t ntiles) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, kq = lane >> 4;
+    h4 A[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) A[t] = *reinterpret_cast<const h4 *>(Wp + (t * 16 + j) * 16 + 4 * kq);
+    float br[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) br[r] = bias[4 * kq + r];
+    const int64_t V = (int64_t)G * G * G;
+    const int xcd = blockIdx.x % 8, lb = blockIdx.x / 8, nlb = gridDim.x / 8;
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t t_lo = xcd * per, t_hi = (t_lo + per < ntiles) ? t_lo + per : ntiles;
+    const h4 zero = {(_Float16)0.f, (_Float16)0.f, (_Float16)0.f, (_Float16)0.f};
+    for (int64_t tile = t_lo + (int64_t)lb * 4 + wave; tile < t_hi; tile += (int64_t)nlb * 4) {
+        const int64_t v = tile * 16 + j;
+        const bool valid = v < V;
+        int x, yy, z;
+        vox_xyz(valid ? v : 0, G, x, yy, z);
+        f4 acc[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t9 = 0; t9 < 9; ++t9) {
+            const int xx = x + d * (t9 % 3 - 1), y2 = yy + d * (t9 / 3 - 1);
+            const bool row_in = valid && xx >= 0 && xx < G && y2 >= 0 && y2 < G;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int zz = z + d * (q - 1);
+                h4 b = zero;
+                if (row_in && zz >= 0 && zz < G)
+                    b = *reinterpret_cast<const h4 *>(in + (((int64_t)zz * G + y2) * G + xx) * 16 + 4 * kq);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + t9], b, acc[q], 0, 0, 0);
+            }
+        }
+        if (valid) {
+            const f4 s = (acc[0] + acc[1]) + acc[2];
+            if (!LAST) {
+                h4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = (_Float16)fmaxf(s[r] + br[r], 0.f);
+                *reinterpret_cast<h4 *>(out + v * 16 + 4 * kq) = o;
+            } else if (kq == 0) {
+                y[v] = s[0] + br[0];
+            }
+        }
+    }
 }
 
 int grid1(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65535); }
@@ -367,24 +493,63 @@ int gradients(bemfft_net *n, const float *x, int64_t nt, const int *vox, const f
     return 0;
 }
 
-double rms_known(const bemfft_plan *p, const double *known, const uint8_t *bc, hipStream_t st, int *status) {
-    const int64_t m = p->m;
-    std::vector<double> hk(m);
-    std::vector<uint8_t> hb(m, 0);
-    if (hipMemcpyAsync(hk.data(), known, m * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        (bc && hipMemcpyAsync(hb.data(), bc, m, hipMemcpyDeviceToHost, st) != hipSuccess) ||
-        hipStreamSynchronize(st) != hipSuccess) {
-        *status = BEMFFT_EDEVICE;
-        return 0.0;
+int input_impl(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const double *known, double s_host,
+               const double *s_dev, float *x, hipStream_t st) {
+    if (p->dim != 3 || p->kernel != BEMFFT_LAPLACE3D || p->n[0] != n->G || p->n[1] != n->G || p->n[2] != n->G) {
+        set_error("net_input: needs a Laplace 3D plan on the network's grid");
+        return BEMFFT_EINVAL;
     }
-    double s = 0.0;
-    int64_t c = 0;
-    for (int64_t j = 0; j < m; ++j)
-        if (hb[j] == 0) {
-            s += hk[j] * hk[j];
-            ++c;
+    if (p->m > n->cap) {
+        BF_HIP(hipStreamSynchronize(st));
+        for (double **q : {&n->dq, &n->du, &n->db}) {
+            if (*q) (void)hipFree(*q);
+            *q = nullptr;
         }
-    return c ? std::sqrt(s / c) : 0.0;
+        n->cap = 0;
+        if (hipMalloc(&n->dq, p->m * 8) != hipSuccess || hipMalloc(&n->du, p->m * 8) != hipSuccess ||
+            hipMalloc(&n->db, p->m * 8) != hipSuccess) {
+            set_error("net_input: allocation failed");
+            return BEMFFT_ENOMEM;
+        }
+        n->cap = p->m;
+    }
+    const unsigned gm = (unsigned)((p->m + 255) / 256);
+    hipLaunchKernelGGL(k_nn_split, dim3(gm), dim3(256), 0, st, bc, known, n->dq, n->du, p->m);
+    BF_HIP(hipGetLastError());
+    BF_CHECK(launch_apply(p, p->eng, n->dq, n->du, n->db, st));
+    hipLaunchKernelGGL(k_fill, dim3(grid1(n->cin * n->V)), dim3(256), 0, st, x, n->cin * n->V, 0.f);
+    hipLaunchKernelGGL(k_nn_input, dim3(gm), dim3(256), 0, st, p->d_gx, p->d_gy, p->d_gz, p->d_perm, p->d_w, p->d_nrm,
+                       known, n->db, bc, p->m, n->G, 1.0 / (p->h * p->h), s_host, s_dev, x, n->V);
+    BF_HIP(hipGetLastError());
+    return 0;
+}
+
+// FP16 inference: x planar FP32 [6][V] -> n->y (FP32 [V])
+int infer(bemfft_net *n, const float *x, hipStream_t st) {
+    const int64_t V = n->V;
+    hipLaunchKernelGGL(k_to_cl16, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, x, n->cin, V, n->ha);
+    hipLaunchKernelGGL(k_pack16, dim3(27, n->nl), dim3(256), 0, st, n->p, n->d_woff, n->d_boff, n->d_ci, n->d_co,
+                       n->wp, n->bp);
+    BF_HIP(hipGetLastError());
+    const int64_t ntiles = (V + 15) / 16;
+    // a multiple of 8 blocks (one share per XCD), at most 8 per CU
+    const int64_t per_xcd = ((ntiles + 7) / 8 + 3) / 4;
+    const unsigned blocks = 8u * (unsigned)std::max<int64_t>(1, std::min<int64_t>(per_xcd, 256));
+    float *y = n->post + (int64_t)(n->nl - 1) * n->width * V;
+    _Float16 *in = n->ha, *out = n->hb;
+    for (int l = 0; l < n->nl; ++l) {
+        const _Float16 *W = n->wp + (int64_t)l * 27 * 256;
+        const float *b = n->bp + l * 16;
+        if (l == n->nl - 1)
+            hipLaunchKernelGGL(k_conv16<true>, dim3(blocks), dim3(256), 0, st, in, W, b, out, y, n->G, n->dil[l], ntiles);
+        else
+            hipLaunchKernelGGL(k_conv16<false>, dim3(blocks), dim3(256), 0, st, in, W, b, out, y, n->G, n->dil[l],
+                               ntiles);
+        BF_HIP(hipGetLastError());
+        std::swap(in, out);
+    }
+    n->y = y;
+    return 0;
 }
 
 }  // namespace
@@ -440,6 +605,15 @@ int bemfft_net_create(bemfft_net **out, int grid, int width, int nlayers, const 
         hipMalloc(&n->gb, (size_t)width * n->V * 4) != hipSuccess ||
         hipMalloc(&n->part, (size_t)nch * width * width * 28 * 4) != hipSuccess ||
         hipMalloc(&n->red, (size_t)65536 * 4) != hipSuccess ||
+        hipMalloc(&n->ha, (size_t)n->V * 16 * 2) != hipSuccess || hipMalloc(&n->hb, (size_t)n->V * 16 * 2) != hipSuccess ||
+        hipMalloc(&n->wp, (size_t)nlayers * 27 * 256 * 2) != hipSuccess ||
+        hipMalloc(&n->bp, (size_t)nlayers * 16 * 4) != hipSuccess || hipMalloc(&n->sdev, 8) != hipSuccess ||
+        hipMalloc(&n->d_woff, nlayers * 8) != hipSuccess || hipMalloc(&n->d_boff, nlayers * 8) != hipSuccess ||
+        hipMalloc(&n->d_ci, nlayers * 4) != hipSuccess || hipMalloc(&n->d_co, nlayers * 4) != hipSuccess ||
+        hipMemcpy(n->d_woff, n->woff.data(), nlayers * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->d_boff, n->boff.data(), nlayers * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->d_ci, n->ci.data(), nlayers * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->d_co, n->co.data(), nlayers * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(n->p, hp.data(), n->nparam * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(n->m, 0, n->nparam * 4) != hipSuccess || hipMemset(n->v, 0, n->nparam * 4) != hipSuccess) {
         bemfft_net_destroy(n);
@@ -454,7 +628,10 @@ int bemfft_net_destroy(bemfft_net *n) {
     if (!n) return 0;
     for (float *q : {n->p, n->g, n->m, n->v, n->pre, n->post, n->ga, n->gb, n->part, n->red})
         if (q) (void)hipFree(q);
-    for (double *q : {n->dq, n->du, n->db})
+    for (double *q : {n->dq, n->du, n->db, n->sdev})
+        if (q) (void)hipFree(q);
+    for (void *q : {(void *)n->ha, (void *)n->hb, (void *)n->wp, (void *)n->bp, (void *)n->d_woff, (void *)n->d_boff,
+                    (void *)n->d_ci, (void *)n->d_co})
         if (q) (void)hipFree(q);
     delete n;
     return 0;
@@ -480,40 +657,21 @@ int bemfft_net_input(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const dou
         set_error("net_input: null argument");
         return BEMFFT_EINVAL;
     }
-    if (p->dim != 3 || p->kernel != BEMFFT_LAPLACE3D || p->n[0] != n->G || p->n[1] != n->G || p->n[2] != n->G) {
-        set_error("net_input: needs a Laplace 3D plan on the network's grid");
-        return BEMFFT_EINVAL;
-    }
-    hipStream_t st = (hipStream_t)stream;
-    if (p->m > n->cap) {
-        BF_HIP(hipStreamSynchronize(st));
-        for (double **q : {&n->dq, &n->du, &n->db}) {
-            if (*q) (void)hipFree(*q);
-            *q = nullptr;
-        }
-        n->cap = 0;
-        if (hipMalloc(&n->dq, p->m * 8) != hipSuccess || hipMalloc(&n->du, p->m * 8) != hipSuccess ||
-            hipMalloc(&n->db, p->m * 8) != hipSuccess) {
-            set_error("net_input: allocation failed");
-            return BEMFFT_ENOMEM;
-        }
-        n->cap = p->m;
-    }
-    const unsigned gm = (unsigned)((p->m + 255) / 256);
-    hipLaunchKernelGGL(k_nn_split, dim3(gm), dim3(256), 0, st, bc, known, n->dq, n->du, p->m);
-    BF_HIP(hipGetLastError());
-    BF_CHECK(launch_apply(p, p->eng, n->dq, n->du, n->db, st));
-    hipLaunchKernelGGL(k_fill, dim3(grid1(n->cin * n->V)), dim3(256), 0, st, x, n->cin * n->V, 0.f);
-    hipLaunchKernelGGL(k_nn_input, dim3(gm), dim3(256), 0, st, p->d_gx, p->d_gy, p->d_gz, p->d_perm, p->d_w, p->d_nrm,
-                       known, n->db, bc, p->m, n->G, 1.0 / (p->h * p->h), scale, x, n->V);
-    BF_HIP(hipGetLastError());
-    return 0;
+    return input_impl(n, p, bc, known, scale, nullptr, x, (hipStream_t)stream);
 }
 
 int bemfft_net_forward(bemfft_net *n, const float *x, float *y, void *stream) {
     if (!n || !x || !y) return BEMFFT_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     BF_CHECK(forward(n, x, st));
+    BF_HIP(hipMemcpyAsync(y, n->y, n->V * 4, hipMemcpyDeviceToDevice, st));
+    return 0;
+}
+
+int bemfft_net_infer(bemfft_net *n, const float *x, float *y, void *stream) {
+    if (!n || !x || !y) return BEMFFT_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    BF_CHECK(infer(n, x, st));
     BF_HIP(hipMemcpyAsync(y, n->y, n->V * 4, hipMemcpyDeviceToDevice, st));
     return 0;
 }
@@ -544,14 +702,12 @@ int bemfft_net_guess(bemfft_net *n, bemfft_plan *p, const uint8_t *bc, const dou
                      double *x0, void *stream) {
     if (!n || !p || !known || !xbuf || !x0) return BEMFFT_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    int status = 0;
-    const double rms = rms_known(p, known, bc, st, &status);
-    BF_CHECK(status);
-    const double s = rms > 0.0 ? 1.0 / rms : 1.0;
-    BF_CHECK(bemfft_net_input(n, p, bc, known, s, xbuf, stream));
-    BF_CHECK(forward(n, xbuf, st));
+    hipLaunchKernelGGL(k_nn_scale, dim3(1), dim3(256), 0, st, known, bc, p->m, n->sdev);
+    BF_HIP(hipGetLastError());
+    BF_CHECK(input_impl(n, p, bc, known, 1.0, n->sdev, xbuf, st));
+    BF_CHECK(infer(n, xbuf, st));
     hipLaunchKernelGGL(k_nn_gather, dim3((unsigned)((p->m + 255) / 256)), dim3(256), 0, st, n->y, p->d_gx, p->d_gy,
-                       p->d_gz, p->d_perm, bc, p->m, n->G, 1.0 / (s * p->h), x0);
+                       p->d_gz, p->d_perm, bc, p->m, n->G, n->sdev, p->h, x0);
     BF_HIP(hipGetLastError());
     return 0;
 }

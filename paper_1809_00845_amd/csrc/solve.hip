@@ -86,12 +86,16 @@ __global__ __launch_bounds__(kRedThreads) void k_mdot_partial(const double *V, i
     }
 }
 
-__global__ void k_mdot_final(const double *partial, int nblk, int nvec, double *out, int sqrt_last) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nvec) return;
+// out[j] = sum over blocks of partial[b][j]: one wavefront per j, each lane
+// a fixed stride of blocks, then a fixed shuffle tree (deterministic)
+__global__ __launch_bounds__(64) void k_mdot_final(const double *partial, int nblk, int nvec, double *out,
+                                                   int sqrt_last) {
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * nvec + j];
-    out[j] = (sqrt_last && j == nvec - 1) ? sqrt(s) : s;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += partial[(int64_t)b * nvec + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) out[j] = (sqrt_last && j == nvec - 1) ? sqrt(s) : s;
 }
 
 // w[i] += sign * sum_j V[j][i] h[j]; eight independent partial sums keep
@@ -171,7 +175,7 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
 int mdot(const double *V, int64_t ld, int nvec, const double *w, int64_t n, double *red, double *out, int sqrt_last,
          hipStream_t st) {
     hipLaunchKernelGGL(k_mdot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, ld, nvec, w, n, red);
-    hipLaunchKernelGGL(k_mdot_final, dim3((nvec + 63) / 64), dim3(64), 0, st, red, kRedBlocks, nvec, out, sqrt_last);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nvec), dim3(64), 0, st, red, kRedBlocks, nvec, out, sqrt_last);
     BF_HIP(hipGetLastError());
     return 0;
 }
@@ -205,7 +209,7 @@ double norm2(const double *v, int64_t n, Ws &ws, double *pinned, hipStream_t st,
 // residual (w.r.t. ||rhs||) through the pointers.
 int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double *rhs, double *x, bool x_zero,
                double tol, int mcap, int maxit, Ws &ws, double *hp, hipStream_t st, int *iters_out, int *restarts_out,
-               double *relres_out) {
+               double *relres_out, const double *r0_given = nullptr) {
     const int64_t n = (int64_t)p->ncomp * p->m;
     int status = 0;
     const double bnorm = norm2(rhs, n, ws, hp, st, &status);
@@ -225,9 +229,11 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         return 0;
     }
     for (;;) {
-        // r0 = rhs - A x
+        // r0 = rhs - A x (on the first cycle the caller may already hold it)
         if (x_zero) {
             BF_HIP(hipMemcpyAsync(ws.w, rhs, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        } else if (r0_given && cycles == 0) {
+            BF_HIP(hipMemcpyAsync(ws.w, r0_given, n * sizeof(double), hipMemcpyDeviceToDevice, st));
         } else {
             BF_CHECK(apply_unknown(p, e, bc, x, nullptr, ws, ws.w, st));
             hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ws.w, rhs, 1.0, -1.0, n);
@@ -387,7 +393,7 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
     }
     if (!o.refine) {
         status = gmres_core(p, p->eng, bc, ws.b, ws.x, !use_x0, o.tol, o.restart, o.maxit, ws, hp, st, &iters,
-                            &restarts, &rel);
+                            &restarts, &rel, o.use_x0 == 2 ? ws.ro : nullptr);
     } else {
         // iterative refinement: r = b - A64 x in FP64, d ~ A^-1 r in the
         // working precision, x += d

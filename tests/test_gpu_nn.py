@@ -97,6 +97,25 @@ def test_net_forward_matches_oracle(dev, G):
     net.close()
 
 
+@pytest.mark.parametrize("G,dil", [(9, (1, 2, 4, 8)), (23, (1, 2, 4, 8)), (32, (1, 2, 4, 8)), (13, (3, 1))])
+def test_net_infer_fp16_matches_oracle(dev, G, dil):
+    """FP16 storage, FP32 accumulation on the matrix cores.  Bar: 1e-2 of
+    max |y| -- FP16 rounding (2^-11) of the inputs of every layer, growing
+    through <= 4 layers of sums of up to 432 products."""
+    net = B.Net(G, dil, seed=1)
+    p = _rand_params(net, 50 + G)
+    x = _sparse_input(G, 60 + G)
+    y = torch.empty(G ** 3, dtype=torch.float32, device=dev)
+    net.infer(torch.tensor(x, device=dev), y)
+    torch.cuda.synchronize()
+    ref = NN.forward(p, list(dil), x.astype(np.float64).reshape(6, G, G, G))[0].ravel()
+    got = y.cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-2 * scale
+    assert np.linalg.norm(got - ref) <= 3e-3 * np.linalg.norm(ref)
+    net.close()
+
+
 @pytest.mark.parametrize("G,dil", [(10, (1, 2, 4, 8)), (23, (1, 2, 4, 8)), (12, (1, 3)), (17, (2, 1, 1))])
 def test_net_gradients_match_oracle(dev, G, dil):
     net = B.Net(G, dil, seed=2)

@@ -218,6 +218,56 @@ def test_config2_cube_full_size_sampled(dev):
     assert err < TOL[B.FP32]
 
 
+@pytest.fixture(scope="module")
+def star192():
+    """Config-3 surface: star r = 0.3(1 + 0.2 sum of 6 real Y_lm, l <= 4,
+    N(0, 1) coefficients, seed 1) on a 192^3 grid."""
+    return I.star3d(192, I.draw_stars(1, 1)[0])
+
+
+def _elastic_dirichlet(g, seed, nu=0.3, mu=1.0):
+    """Linear displacement u = E x (E random, seeded) given everywhere; the
+    traction is sought."""
+    E = np.random.default_rng(seed).normal(size=(3, 3))
+    u = (g.rel() @ E.T).T
+    return np.zeros((3, g.m), dtype=np.uint8), u
+
+
+def test_config3_navier_star_full_size_sampled(dev, star192):
+    """Navier (Kelvin), nu = 0.3, mu = 1, on the 192^3 star padded to 384^3
+    (24 kernel spectra): every output from the GPU, a contiguous sample of
+    targets (all three components) from the oracle."""
+    g = star192
+    assert 60000 <= g.m <= 100000
+    for prec in (B.FP32, B.FP64):
+        err, info = _parity(dev, g, B.NAVIER3D, prec, nu=0.3, mu=1.0, targets=(2000, 2120))
+        assert info["pad"] == [384, 384, 384] and info["nspectra"] == 24
+        assert err < TOL[prec], (prec, err)
+
+
+def test_config3_navier_star_refined_solve(dev, star192):
+    """FP32 transforms with FP64 refinement on the 192^3 Navier star
+    (displacement given, traction sought): the true FP64 residual meets the
+    tolerance and the solution matches the plain FP64 GPU solve (the oracle's
+    dense LU is out of reach at 200k unknowns; the small-size Navier solves
+    are pinned to it)."""
+    g = star192
+    bc, known = _elastic_dirichlet(g, 11)
+    bct, kt = _t(bc, dev), _t(known, dev)
+    p32 = B.Plan(g, B.NAVIER3D, precision=B.FP32, nu=0.3, mu=1.0, keep_fp64=True)
+    x32, i32 = p32.solve(bct, kt, tol=1e-8, refine=1, inner_tol=1e-3)
+    assert i32["status"] == 0 and i32["true_relres"] <= 1e-8 and i32["outer"] >= 2
+    p32.close()
+    p64 = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=0.3, mu=1.0)
+    x64, i64 = p64.solve(bct, kt, tol=1e-8)
+    assert i64["status"] == 0 and i64["true_relres"] <= 1e-8
+    p64.close()
+    a, b = x32.cpu().numpy(), x64.cpu().numpy()
+    # both residuals <= 1e-8: the solutions differ by at most cond(A) * 2e-8
+    # (measured ratio of solution difference to residual: ~2e2)
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5
+
+
 def test_apply_is_deterministic(dev):
     g = I.sphere3d(48, 0.35)
     rng = np.random.default_rng(2)
