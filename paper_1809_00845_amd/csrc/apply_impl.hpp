@@ -371,25 +371,45 @@ __device__ __forceinline__ void zpass_body(const ApplyArgs &a, const int bx, con
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[o][e] = {R(0), R(0)};
 
+    // Row and spectrum addressing, hoisted out of the element loops: lane t
+    // holds z = t + e*TPP; elements e < E/2 lie in the lower half (kz < P/2,
+    // read straight from the octant), e >= E/2 in the upper half (kz >= P/2,
+    // read at P - kz with the z-reflection sign; kz = P/2 reads the Nyquist
+    // plane, where every z-odd spectrum is zero, so its sign is immaterial).
+    const int zoff = t - a.z0;
+    const int64_t estride = (int64_t)TPP * a.py;
+    const size_t fstride = (size_t)a.hx * a.nzo * a.py;
+    const cx<R> *Yl = static_cast<const cx<R> *>(a.Y) + (size_t)kx * a.nzo * a.py + (int64_t)zoff * a.py + ky;
+    const int kyp = ky < a.hy ? ky : a.py - ky;
+    const bool fy = ky >= a.hy;
+    const R *srow = spec + ((size_t)kx * a.hy + kyp) * a.hz;
+    const size_t cstride = (size_t)a.hx * a.hy * a.hz;
+
     static_for<0, F>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
-        const cx<R> *Yf = static_cast<const cx<R> *>(a.Y) + (size_t)(f * a.hx + kx) * a.nzo * a.py;
+        const cx<R> *Yf = Yl + f * fstride;
         cx<R> x[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int zz = t + e * TPP - a.z0;  // occupied plane index; others are zero
-            x[e] = (live && zz >= 0 && zz < a.nzo) ? Yf[(size_t)zz * a.py + ky] : cx<R>{R(0), R(0)};
+            // planes z >= P/2 are padding (the grid spans at most P/2 planes)
+            const int zz = zoff + e * TPP;  // occupied plane index; others are zero
+            if (e >= E / 2) x[e] = cx<R>{R(0), R(0)};
+            else x[e] = (live && zz >= 0 && zz < a.nzo) ? Yf[e * estride] : cx<R>{R(0), R(0)};
         }
         fft_regs_s<R, SH, -1>(x, pb, tw, t);
         if (live) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int kz = t + e * TPP;
+                const int kzp = e < E / 2 ? kz : PZ - kz;
                 static_for<0, T::N>([&](auto tc) {
                     constexpr int term = decltype(tc)::value;
                     if constexpr (T::f(term) == f) {
                         constexpr int c = T::c(term);
-                        mac<R>(acc[T::o(term)][e], x[e], spec_at<R, KIND>(spec, a, c, kx, ky, kz), comp_imag(KIND, c));
+                        constexpr int mask = comp_oddmask(KIND, c);
+                        const R sv = srow[c * cstride + kzp];
+                        const bool flip = (fy && (mask & 2)) != ((e >= E / 2) && (mask & 4));
+                        mac<R>(acc[T::o(term)][e], x[e], flip ? -sv : sv, comp_imag(KIND, c));
                     }
                 });
             }
@@ -400,19 +420,30 @@ __device__ __forceinline__ void zpass_body(const ApplyArgs &a, const int bx, con
     for (int o = 0; o < O; ++o) {
         fft_regs_s<R, SH, 1>(acc[o], pb, tw, t);
         if (live) {
-            cx<R> *Zo = static_cast<cx<R> *>(a.Z) + (size_t)(o * a.hx + kx) * a.nzo * a.py;
+            cx<R> *Zl = static_cast<cx<R> *>(a.Z) + (size_t)(o * a.hx + kx) * a.nzo * a.py + (int64_t)zoff * a.py + ky;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int zz = t + e * TPP - a.z0;
-                if (zz >= 0 && zz < a.nzo) Zo[(size_t)zz * a.py + ky] = acc[o][e];
+            for (int e = 0; e < E / 2; ++e) {  // outputs z >= P/2 are never needed
+                const int zz = zoff + e * TPP;
+                if (zz >= 0 && zz < a.nzo) Zl[e * estride] = acc[o][e];
             }
         }
     }
 }
 
+// One-dimensional grid of 8 * ceil(hx * nby / 8) blocks.  Blocks go to the
+// 8 XCDs round-robin, so block b runs on XCD b % 8; each XCD is given one
+// contiguous run of (kx, ky-block) work items, ordered so that the blocks of
+// one kx and their mirrored ky blocks (which read the same octant rows of
+// the spectra) follow each other on the same L2.
 template <typename R, typename SH, int KIND>
-__global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a) {
-    zpass_body<R, SH, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__((ZCfg<R, SH, KIND>::NT)) void k_zpass(ApplyArgs a, int nby) {
+    const int total = a.hx * nby;
+    const int per = (total + 7) / 8;
+    const int lam = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (lam >= total) return;
+    const int kx = lam / nby, j = lam % nby;
+    const int by = (j & 1) ? nby - 1 - (j >> 1) : (j >> 1);
+    zpass_body<R, SH, KIND>(a, kx, by, 0);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -616,8 +647,9 @@ int launch_z(const ApplyArgs &a, hipStream_t st) {
     } else {
         using SH = Sched<PZ, SCHED>;
         using Cfg = ZCfg<R, SH, KIND>;
-        dim3 grid(a.hx, (a.py + Cfg::TY - 1) / Cfg::TY);
-        hipLaunchKernelGGL((k_zpass<R, SH, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+        const int nby = (a.py + Cfg::TY - 1) / Cfg::TY;
+        const int per = (a.hx * nby + 7) / 8;
+        hipLaunchKernelGGL((k_zpass<R, SH, KIND>), dim3(8 * per), dim3(Cfg::NT), 0, st, a, nby);
     }
     BF_HIP(hipGetLastError());
     return 0;

@@ -36,6 +36,23 @@ __global__ void k_split(const uint8_t *bc, const double *x, const double *scale,
     }
 }
 
+// The next Krylov vector and the split of its scaled copy in one pass:
+// v = w / norm (norm read from device memory) is stored as the basis column,
+// and v * scale goes into the unknown slots of (q, u) for the apply.
+__global__ void k_split_norm(const uint8_t *bc, const double *w, const double *norm, const double *scale, double *v_out,
+                             double *q, double *u, int64_t n) {
+    const double a = *norm;
+    const double inv = a > 0.0 ? 1.0 / a : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = w[i] * inv;
+        v_out[i] = v;
+        const double vs = v * scale[i];
+        const bool qslot = bc[i] == 0;  // unknown: q where u is known
+        q[i] = qslot ? vs : 0.0;
+        u[i] = qslot ? 0.0 : vs;
+    }
+}
+
 __global__ void k_axpby(double *y, const double *x, double a, double b, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = a * x[i] + b * y[i];
@@ -112,6 +129,32 @@ __global__ void k_gemv(const double *V, int64_t ld, int nvec, const double *h, d
         const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         w[i] += sign * s;
     }
+}
+
+// w[i] -= sum_j V[j][i] h[j] as k_gemv, and each block's sum of the updated
+// w[i]^2 into partial[block] (fixed-order reduction: reproducible)
+__global__ __launch_bounds__(256) void k_gemv_norm(const double *V, int64_t ld, int nvec, const double *h, double *w,
+                                                   int64_t n, double *partial) {
+    __shared__ double sm[4];
+    double ss = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int j = 0;
+        for (; j + 8 <= nvec; j += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        }
+        for (int k = 0; j + k < nvec; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        const double wi = w[i] - s;
+        w[i] = wi;
+        ss += wi * wi;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
 }
 
 // v = w / norm, norm read from device memory
@@ -258,17 +301,24 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         bool breakdown = false;
         for (; k < mcap && iters < maxit; ++k) {
             double *vk = ws.V + (int64_t)k * n;
-            // w = A Dinv v_k
-            BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
-            // classical Gram-Schmidt, twice
             double *h1 = ws.hd, *h2 = ws.hd + 512;
+            // w = A Dinv v_k; for k > 0, v_k = w / ||w|| of the previous step is
+            // formed in the same pass that splits it into the apply's slots
+            if (k == 0) {
+                BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
+            } else {
+                hipLaunchKernelGGL(k_split_norm, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, h2 + k, ws.dinv, vk,
+                                   ws.q, ws.u, n);
+                BF_HIP(hipGetLastError());
+                BF_CHECK(launch_apply(p, e, ws.q, ws.u, ws.w, st));
+            }
+            // classical Gram-Schmidt, twice; the second update also sums ||w||^2
             BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h1, 0, st));
             hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h1, ws.w, n, -1.0);
             BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h2, 0, st));
-            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h2, ws.w, n, -1.0);
-            BF_CHECK(mdot(ws.w, n, 1, ws.w, n, ws.red, h2 + k + 1, 1, st));
-            hipLaunchKernelGGL(k_normalize, dim3(grid_for(n)), dim3(256), 0, st, ws.w, h2 + k + 1,
-                               ws.V + (int64_t)(k + 1) * n, n);
+            const int gn = grid_for(n);
+            hipLaunchKernelGGL(k_gemv_norm, dim3(gn), dim3(256), 0, st, ws.V, n, k + 1, h2, ws.w, n, ws.red);
+            hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, st, ws.red, gn, 1, h2 + k + 1, 1);
             BF_HIP(hipGetLastError());
             BF_HIP(hipMemcpyAsync(hp, ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
             BF_HIP(hipStreamSynchronize(st));
