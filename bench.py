@@ -212,7 +212,7 @@ def bench_navier_star(B, I, dev, steps):
     r = torch.empty_like(u)
     out = {"nodes": g.m, "grid": 192, "pad": 384, "voxelise_s": t_geom}
     p32 = B.Plan(g, B.NAVIER3D, precision=B.FP32, nu=0.3, mu=1.0, keep_fp64=True, autotune=1)
-    p64 = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=0.3, mu=1.0)
+    p64 = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=0.3, mu=1.0, autotune=1)
     n32, n64 = max(20, steps // 4), max(10, steps // 10)
     out["fp32_matvec_s"] = n32 / timed_applies(p32, q, u, r, n32, 5)
     out["fp64_matvec_s"] = n64 / timed_applies(p64, q, u, r, n64, 3)
@@ -222,7 +222,7 @@ def bench_navier_star(B, I, dev, steps):
     E = np.random.default_rng(11).normal(size=(3, 3))
     uu = (g.rel() @ E.T).T
     bct = torch.zeros((3, g.m), dtype=torch.uint8, device=dev)
-    known = torch.tensor(uu, device=dev)
+    known = torch.tensor(np.ascontiguousarray(uu), device=dev)
     solves = {}
     for tag, pl, kw in (("fp64", p64, {}), ("fp32", p32, {}), ("fp32_refined_fp64", p32, {"refine": 1, "inner_tol": 1e-3})):
         pl.solve(bct, known, tol=1e-6, **kw)
@@ -426,7 +426,7 @@ def main():
     if not args.quick:
         extra = {}
         # FP64 apply, same cube
-        plan64 = B.Plan(cube, B.LAPLACE3D, precision=B.FP64)
+        plan64 = B.Plan(cube, B.LAPLACE3D, precision=B.FP64, autotune=1)
         dt64 = timed_applies(plan64, q, u, r, max(20, args.steps // 4), 5)
         extra["cube_fp64_matvec_s"] = max(20, args.steps // 4) / dt64
         # sphere

@@ -271,7 +271,7 @@ class Plan:
         import torch
 
         if unknown is None:
-            unknown = torch.zeros_like(known)
+            unknown = torch.zeros_like(known, memory_format=torch.contiguous_format)
             kw.setdefault("use_x0", 0)
         info = bemfft_solve(self.handle, bc, known, unknown, **kw)
         return unknown, info

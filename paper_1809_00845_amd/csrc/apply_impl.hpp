@@ -244,7 +244,10 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
         const int kxl = pr % KXC, y = pr / KXC, kx = kx0 + kxl;
         if (kx >= a.hx) continue;
         const int row = zz * a.ny + y;
+        // the row's bounds and its long-row slot are independent loads: issue
+        // them together so the node loads wait on one round trip, not two
         const int dense = a.row_dense[row];
+        const int r0 = a.rowptr[row], r1 = a.rowptr[row + 1];
         cx<R> acc[F];
         if (dense >= 0) {
 #pragma unroll
@@ -252,9 +255,8 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
         } else {
 #pragma unroll
             for (int f = 0; f < F; ++f) acc[f] = {R(0), R(0)};
-            const int s0 = a.rowptr[row], s1 = a.rowptr[row + 1];
 #pragma unroll 4
-            for (int s = s0; s < s1; ++s) {
+            for (int s = r0; s < r1; ++s) {
                 const cx<R> w = twx[mod_small(kx, a.gx[s], a.px, inv_px)];
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
@@ -275,8 +277,9 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
     cx<R> x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
+        // rows y >= P/2 lie beyond the grid (ny <= P/2): zero at compile time
         const int y = t + e * TPP;
-        x[e] = y < a.ny ? pb[pslot(y)] : cx<R>{R(0), R(0)};
+        x[e] = (e < E / 2 && y < a.ny) ? pb[pslot(y)] : cx<R>{R(0), R(0)};
     }
     fft_regs<R, PY, -1>(x, pb, tw, t);
     if (kx < a.hx) {
@@ -541,7 +544,7 @@ __device__ __forceinline__ void inv_yx_body(const ApplyArgs &a, const int bx, co
     fft_regs<R, PY, 1>(x, pb, tw, t);
     wave_lds_sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < E / 2; ++e) {  // rows y >= P/2 are never gathered
         const int y = t + e * TPP;
         if (y < a.ny) pb[pslot(y)] = x[e];
     }

@@ -262,7 +262,7 @@ template <> struct Sched<256, 1> : FFTShape<256, 32, 8, 8, 4> {};
 template <> struct Sched<320, 0> : FFTShape<320, 16, 4, 4, 20> {};
 template <> struct Sched<320, 1> : FFTShape<320, 16, 20, 4, 4> {};
 template <> struct Sched<384, 0> : FFTShape<384, 16, 8, 6, 8> {};
-template <> struct Sched<384, 1> : FFTShape<384, 16, 6, 8, 8> {};
+template <> struct Sched<384, 1> : FFTShape<384, 32, 4, 4, 4, 6> {};
 template <> struct Sched<512, 0> : FFTShape<512, 32, 8, 8, 8> {};
 template <> struct Sched<512, 1> : FFTShape<512, 32, 16, 4, 8> {};
 
