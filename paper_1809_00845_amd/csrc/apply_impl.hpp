@@ -134,6 +134,26 @@ __global__ __launch_bounds__(256) void kb_fields(const ApplyArgs *members, const
     fields_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
 }
 
+// Value of field f at sorted node s, computed from q and u exactly as
+// fields_body stores it (same operations, same rounding), for kernels that
+// must not wait for k_fields.
+template <typename R, int KIND>
+__device__ __forceinline__ R field_value(const ApplyArgs &a, const int s, const int f) {
+    const int j = a.perm[s];
+    const double wt = a.w[s];
+    if constexpr (KIND == 0 || KIND == 1) {
+        if (f == 0) return (R)(a.q[j] * wt);
+        const double uw = a.u[j] * wt;
+        return (R)(uw * a.nrm[(f - 1) * a.m + s]);
+    } else {
+        if (f < 3) return (R)(a.q[f * a.m + j] * wt);
+        const int p = f - 3, i = pair_i(p), k = pair_j(p);
+        const double ui = a.u[i * a.m + j], uk = a.u[k * a.m + j];
+        const double ni = a.nrm[i * a.m + s], nk = a.nrm[k * a.m + s];
+        return (R)((i == k ? ui * ni : ui * nk + uk * ni) * wt);
+    }
+}
+
 // ------------------------------------------------------------------ k_rows_fft
 // Long grid rows (e.g. rows of a box face lying in a grid plane) are
 // x-transformed with an FFT instead of the direct sum: the row's nodes are
@@ -154,7 +174,6 @@ __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, 
     __shared__ cx<R> tw[PX];
     const int tid = threadIdx.x;
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
-    const R *vf = static_cast<const R *>(a.vf);
     for (int i = tid; i < PX; i += 256) tw[i] = gtwx[i];
     const int pen = tid / TPP, t = tid % TPP;
     const int pid = bx * PPB + pen;  // (dense row, field)
@@ -170,8 +189,8 @@ __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, 
         for (int s = s0 + t; s < s1; s += TPP) {
             const int x = a.gx[s];
             if (s > s0 && a.gx[s - 1] == x) continue;  // summed by the first node of the cell
-            R v = vf[f * a.m + s];
-            for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) v += vf[f * a.m + s2];
+            R v = field_value<R, KIND>(a, s, f);
+            for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) v += field_value<R, KIND>(a, s2, f);
             pb[pslot(x)] = {v, R(0)};
         }
     }
@@ -194,6 +213,14 @@ __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, 
 template <typename R, int PX, int KIND>
 __global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
     rows_fft_body<R, PX, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// k_fields and k_rows_fft in one launch (they no longer depend on each
+// other): the first nfb blocks scatter the fields, the rest transform rows.
+template <typename R, int PX, int KIND>
+__global__ __launch_bounds__(256) void k_fields_rows(ApplyArgs a, int nfb) {
+    if ((int)blockIdx.x < nfb) fields_body<R, KIND>(a, blockIdx.x, 0, 0);
+    else rows_fft_body<R, PX, KIND>(a, blockIdx.x - nfb, 0, 0);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -677,8 +704,9 @@ struct Launch {
     template <int P> static int fwd(const ApplyArgs &a, hipStream_t st) { return launch_fwd<R, P, KIND>(a, st); }
     template <int P> static int rows(const ApplyArgs &a, hipStream_t st) {
         using Cfg = RowCfg<R, P, KIND>;
-        dim3 grid((Terms<KIND>::F * a.nd + Cfg::PPB - 1) / Cfg::PPB);
-        hipLaunchKernelGGL((k_rows_fft<R, P, KIND>), grid, dim3(256), 0, st, a);
+        const int nfb = (a.m + 255) / 256;
+        const int nrb = (Terms<KIND>::F * a.nd + Cfg::PPB - 1) / Cfg::PPB;
+        hipLaunchKernelGGL((k_fields_rows<R, P, KIND>), dim3(nfb + nrb), dim3(256), 0, st, a, nfb);
         BF_HIP(hipGetLastError());
         return 0;
     }
@@ -691,8 +719,11 @@ struct Launch {
     // ev (optional): five events recorded around the four stages.
     static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
         if (ev) BF_HIP(hipEventRecord(ev[0], st));
-        hipLaunchKernelGGL((k_fields<R, KIND>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);
-        if (a.nd > 0) BF_CHECK(dispatch_rows(a, st));
+        if (a.nd > 0) {
+            BF_CHECK(dispatch_rows(a, st));  // fields and long-row transforms, one launch
+        } else {
+            hipLaunchKernelGGL((k_fields<R, KIND>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);
+        }
         BF_CHECK(dispatch_fwd(a, st));
         if (ev) BF_HIP(hipEventRecord(ev[1], st));
         BF_CHECK(dispatch_z(a, st));
