@@ -241,7 +241,7 @@ struct FwdCfg {
     static constexpr int TPP = PencilShape<PY>::TPP;
     static constexpr int CB = (int)sizeof(cx<R>);
     static constexpr int PS = pstride<PY>();
-    static constexpr int FIXED = (PY + kMaxPx) * CB;
+    static constexpr int FIXED = PY * CB;
     static constexpr int KXC = clampi(mini(256 / (F * TPP), (64 * 1024 - FIXED) / (F * PS * CB)), 1, 4);
     static constexpr int NT = F * KXC * TPP;
 };
@@ -253,7 +253,6 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
     constexpr int F = Cfg::F, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
     __shared__ cx<R> buf[F * KXC * PS];
     __shared__ cx<R> tw[PY];
-    __shared__ cx<R> twx[kMaxPx];
     const int tid = threadIdx.x;
     const int kx0 = bx * KXC;
     const int zz = by;
@@ -262,7 +261,6 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
     const R *vf = static_cast<const R *>(a.vf);
     const cx<R> *Xd = static_cast<const cx<R> *>(a.Xd);
     for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
-    for (int i = tid; i < a.px; i += NT) twx[i] = gtwx[i];
     __syncthreads();
     const float inv_px = 1.0f / (float)a.px;
     // x-transform of the zero-extended fields for rows y < ny: a direct DFT
@@ -284,7 +282,7 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
             for (int f = 0; f < F; ++f) acc[f] = {R(0), R(0)};
 #pragma unroll 4
             for (int s = r0; s < r1; ++s) {
-                const cx<R> w = twx[mod_small(kx, a.gx[s], a.px, inv_px)];
+                const cx<R> w = gtwx[mod_small(kx, a.gx[s], a.px, inv_px)];  // through the caches
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     const R vv = vf[f * a.m + s];
