@@ -154,7 +154,7 @@ __device__ __forceinline__ R field_value(const ApplyArgs &a, const int s, const 
     }
 }
 
-// ------------------------------------------------------------------ k_rows_fft
+// ------------------------------------------------------------------ long rows
 // Long grid rows (e.g. rows of a box face lying in a grid plane) are
 // x-transformed with an FFT instead of the direct sum: the row's nodes are
 // placed on a zero pencil (nodes sharing a cell are summed in order) and
@@ -210,12 +210,7 @@ __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, 
     }
 }
 
-template <typename R, int PX, int KIND>
-__global__ __launch_bounds__(256) void k_rows_fft(ApplyArgs a) {
-    rows_fft_body<R, PX, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-// k_fields and k_rows_fft in one launch (they no longer depend on each
+// Field scatter and long-row transforms in one launch (they do not depend on each
 // other): the first nfb blocks scatter the fields, the rest transform rows.
 template <typename R, int PX, int KIND>
 __global__ __launch_bounds__(256) void k_fields_rows(ApplyArgs a, int nfb) {
