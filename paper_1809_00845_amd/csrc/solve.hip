@@ -66,40 +66,38 @@ __global__ void k_diag(const uint8_t *bc, const double *ddir, const double *dneu
 }
 
 // partial[blk][j] = sum over this block's rows of V[j][i] w[i], j < nvec.
-// Eight vectors per sweep over the rows; wavefront sums by lane shuffles,
-// then one LDS step across the block's four wavefronts (fixed order: the
-// result is bitwise reproducible).
+// blockIdx.y picks a group of eight vectors, so every group's loads are in
+// flight at once; wavefront sums by lane shuffles, then one LDS step across
+// the block's four wavefronts (fixed order: bitwise reproducible).
 __global__ __launch_bounds__(kRedThreads) void k_mdot_partial(const double *V, int64_t ld, int nvec,
                                                               const double *w, int64_t n, double *partial) {
     constexpr int G = 8;
     constexpr int NW = kRedThreads / 64;
     __shared__ double sm[NW][G];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    for (int j0 = 0; j0 < nvec; j0 += G) {
-        double acc[G];
+    const int j0 = blockIdx.y * G;
+    double acc[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) acc[k] = 0.0;
-        for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
-            const double wi = w[i];
-#pragma unroll
-            for (int k = 0; k < G; ++k)
-                if (j0 + k < nvec) acc[k] += V[(int64_t)(j0 + k) * ld + i] * wi;
-        }
+    for (int k = 0; k < G; ++k) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+        const double wi = w[i];
 #pragma unroll
         for (int k = 0; k < G; ++k)
+            if (j0 + k < nvec) acc[k] += V[(int64_t)(j0 + k) * ld + i] * wi;
+    }
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
-        if (lane == 0)
+    for (int k = 0; k < G; ++k)
 #pragma unroll
-            for (int k = 0; k < G; ++k) sm[wave][k] = acc[k];
-        __syncthreads();
-        if (threadIdx.x < G && j0 + threadIdx.x < nvec) {
-            double s = 0.0;
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    if (lane == 0)
 #pragma unroll
-            for (int q = 0; q < NW; ++q) s += sm[q][threadIdx.x];
-            partial[(int64_t)blockIdx.x * nvec + j0 + threadIdx.x] = s;
-        }
-        __syncthreads();
+        for (int k = 0; k < G; ++k) sm[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < G && j0 + threadIdx.x < nvec) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s += sm[q][threadIdx.x];
+        partial[(int64_t)blockIdx.x * nvec + j0 + threadIdx.x] = s;
     }
 }
 
@@ -193,7 +191,7 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
         if (hipMalloc(&p->s_vec, 9 * (size_t)n * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->s_red, (size_t)kRedBlocks * 512 * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->s_hbuf, 2 * 512 * sizeof(double)) != hipSuccess ||
-            hipHostMalloc(&p->h_pinned, 2 * 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc(&p->h_pinned, 4 * 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             set_error("GMRES workspace allocation failed");
             return BEMFFT_ENOMEM;
         }
@@ -217,7 +215,8 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
 // out[0..nvec) = V[0..nvec)^T w  (and sqrt of the last if sqrt_last)
 int mdot(const double *V, int64_t ld, int nvec, const double *w, int64_t n, double *red, double *out, int sqrt_last,
          hipStream_t st) {
-    hipLaunchKernelGGL(k_mdot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, V, ld, nvec, w, n, red);
+    hipLaunchKernelGGL(k_mdot_partial, dim3(kRedBlocks, (nvec + 7) / 8), dim3(kRedThreads), 0, st, V, ld, nvec, w, n,
+                       red);
     hipLaunchKernelGGL(k_mdot_final, dim3(nvec), dim3(64), 0, st, red, kRedBlocks, nvec, out, sqrt_last);
     BF_HIP(hipGetLastError());
     return 0;
@@ -255,6 +254,14 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
                double *relres_out, const double *r0_given = nullptr) {
     const int64_t n = (int64_t)p->ncomp * p->m;
     int status = 0;
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    for (hipEvent_t &x : evs.e) BF_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     const double bnorm = norm2(rhs, n, ws, hp, st, &status);
     BF_CHECK(status);
     int iters = 0, cycles = 0;
@@ -299,33 +306,46 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         g[0] = beta;
         int k = 0;
         bool breakdown = false;
-        for (; k < mcap && iters < maxit; ++k) {
-            double *vk = ws.V + (int64_t)k * n;
+        // Step kk is queued one step ahead: step k + 1 goes to the GPU before
+        // the host waits for step k's Hessenberg column (its inputs are all on
+        // the device), so the GPU keeps working while the host applies the
+        // rotations.  Each step copies its column to its own half of the
+        // pinned buffer; a step queued past convergence only fills scratch.
+        auto queue_step = [&](int kk) -> int {
+            double *vk = ws.V + (int64_t)kk * n;
             double *h1 = ws.hd, *h2 = ws.hd + 512;
             // w = A Dinv v_k; for k > 0, v_k = w / ||w|| of the previous step is
             // formed in the same pass that splits it into the apply's slots
-            if (k == 0) {
+            if (kk == 0) {
                 BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
             } else {
-                hipLaunchKernelGGL(k_split_norm, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, h2 + k, ws.dinv, vk,
+                hipLaunchKernelGGL(k_split_norm, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, h2 + kk, ws.dinv, vk,
                                    ws.q, ws.u, n);
                 BF_HIP(hipGetLastError());
                 BF_CHECK(launch_apply(p, e, ws.q, ws.u, ws.w, st));
             }
             // classical Gram-Schmidt, twice; the second update also sums ||w||^2
-            BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h1, 0, st));
-            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k + 1, h1, ws.w, n, -1.0);
-            BF_CHECK(mdot(ws.V, n, k + 1, ws.w, n, ws.red, h2, 0, st));
+            BF_CHECK(mdot(ws.V, n, kk + 1, ws.w, n, ws.red, h1, 0, st));
+            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, kk + 1, h1, ws.w, n, -1.0);
+            BF_CHECK(mdot(ws.V, n, kk + 1, ws.w, n, ws.red, h2, 0, st));
             const int gn = grid_for(n);
-            hipLaunchKernelGGL(k_gemv_norm, dim3(gn), dim3(256), 0, st, ws.V, n, k + 1, h2, ws.w, n, ws.red);
-            hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, st, ws.red, gn, 1, h2 + k + 1, 1);
+            hipLaunchKernelGGL(k_gemv_norm, dim3(gn), dim3(256), 0, st, ws.V, n, kk + 1, h2, ws.w, n, ws.red);
+            hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, st, ws.red, gn, 1, h2 + kk + 1, 1);
             BF_HIP(hipGetLastError());
-            BF_HIP(hipMemcpyAsync(hp, ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
-            BF_HIP(hipStreamSynchronize(st));
+            BF_HIP(hipMemcpyAsync(hp + 1024 * (kk & 1), ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
+            BF_HIP(hipEventRecord(evs.e[kk & 1], st));
+            return 0;
+        };
+        const int kmax = std::min(mcap, maxit - iters);
+        BF_CHECK(queue_step(0));
+        for (; k < kmax; ++k) {
+            if (k + 1 < kmax) BF_CHECK(queue_step(k + 1));
+            BF_HIP(hipEventSynchronize(evs.e[k & 1]));
+            const double *hk = hp + 1024 * (k & 1);
             ++iters;
             double *col = &H[(size_t)k * (mcap + 1)];
-            for (int i = 0; i <= k; ++i) col[i] = hp[i] + hp[512 + i];
-            col[k + 1] = hp[512 + k + 1];
+            for (int i = 0; i <= k; ++i) col[i] = hk[i] + hk[512 + i];
+            col[k + 1] = hk[512 + k + 1];
             for (int i = 0; i <= k + 1; ++i)
                 if (!std::isfinite(col[i])) breakdown = true;
             if (breakdown) break;
@@ -343,7 +363,7 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
             g[k + 1] = -sn[k] * g[k];
             g[k] = cs[k] * g[k];
             const double est = std::fabs(g[k + 1]) / bnorm;
-            if (est <= tol || hp[512 + k + 1] == 0.0) {
+            if (est <= tol || hk[512 + k + 1] == 0.0) {
                 ++k;
                 break;
             }
