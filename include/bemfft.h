@@ -302,7 +302,8 @@ int bemfft_net_forward(bemfft_net *n, const float *x, float *y, void *stream);
 int bemfft_net_infer(bemfft_net *n, const float *x, float *y, void *stream);
 
 /* Loss sum_i wt_i (y(vox_i) - tgt_i)^2 of input x (all device arrays, nt
- * targets, vox = z*n*n + y*n + x) and its gradient with respect to every
+ * targets, 1 <= nt <= 2^24, vox = z*n*n + y*n + x; a target whose voxel lies
+ * outside [0, n^3) is ignored) and its gradient with respect to every
  * parameter (written to grad_host if not NULL, num_params floats).
  * Deterministic except for voxels that hold several targets.  Synchronises
  * the stream.  Errors: EINVAL, EDEVICE. */

@@ -49,6 +49,7 @@ namespace bemfft {
 namespace {
 
 constexpr int kChunk = 8192;  // voxels per weight-gradient block
+constexpr int64_t kMaxTargets = 65536LL * 256;  // loss partial sums: one per 256 targets
 
 __device__ __forceinline__ void vox_xyz(int64_t v, int G, int &x, int &y, int &z) {
     x = (int)(v % G);
@@ -247,15 +248,19 @@ __global__ void k_conv_w_reduce(const float *part, int nchunk, int cin, int cout
 }
 
 // weighted squared error at the node voxels; dL/dy scattered into gy
-__global__ void k_nn_loss(const float *y, const int *vox, const float *tgt, const float *wt, int64_t nt, float *gy,
-                          float *red) {
+// (targets whose voxel lies outside [0, V) are skipped: no access is made)
+__global__ void k_nn_loss(const float *y, const int *vox, const float *tgt, const float *wt, int64_t nt, int64_t V,
+                          float *gy, float *red) {
     __shared__ float sm[4];
     const int64_t i = blockIdx.x * 256 + threadIdx.x;
     float l = 0.f;
     if (i < nt) {
-        const float e = y[vox[i]] - tgt[i];
-        l = wt[i] * e * e;
-        atomicAdd(&gy[vox[i]], 2.f * wt[i] * e);
+        const int v = vox[i];
+        if (v >= 0 && v < V) {
+            const float e = y[v] - tgt[i];
+            l = wt[i] * e * e;
+            atomicAdd(&gy[v], 2.f * wt[i] * e);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
     if (threadIdx.x % 64 == 0) sm[threadIdx.x / 64] = l;
@@ -464,7 +469,7 @@ int gradients(bemfft_net *n, const float *x, int64_t nt, const int *vox, const f
     float *gcur = n->ga, *gnext = n->gb;
     hipLaunchKernelGGL(k_fill, dim3(grid1(n->V)), dim3(256), 0, st, gcur, n->V, 0.f);
     const int nb = (int)((nt + 255) / 256);
-    hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(256), 0, st, n->y, vox, tgt, wt, nt, gcur, n->red);
+    hipLaunchKernelGGL(k_nn_loss, dim3(nb), dim3(256), 0, st, n->y, vox, tgt, wt, nt, n->V, gcur, n->red);
     BF_HIP(hipGetLastError());
     std::vector<float> hred(nb);
     BF_HIP(hipMemcpyAsync(hred.data(), n->red, nb * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -678,7 +683,10 @@ int bemfft_net_infer(bemfft_net *n, const float *x, float *y, void *stream) {
 
 int bemfft_net_gradients(bemfft_net *n, const float *x, int64_t nt, const int *vox, const float *tgt, const float *wt,
                          double *loss, float *grad_host, void *stream) {
-    if (!n || !x || nt < 1 || !vox || !tgt || !wt) return BEMFFT_EINVAL;
+    if (!n || !x || nt < 1 || nt > kMaxTargets || !vox || !tgt || !wt) {
+        set_error("net_gradients: null argument or target count outside [1, 2^24]");
+        return BEMFFT_EINVAL;
+    }
     BF_CHECK(gradients(n, x, nt, vox, tgt, wt, loss, (hipStream_t)stream));
     if (grad_host) BF_HIP(hipMemcpy(grad_host, n->g, n->nparam * 4, hipMemcpyDeviceToHost));
     return 0;
@@ -686,7 +694,10 @@ int bemfft_net_gradients(bemfft_net *n, const float *x, int64_t nt, const int *v
 
 int bemfft_net_train_step(bemfft_net *n, const float *x, int64_t nt, const int *vox, const float *tgt, const float *wt,
                           float lr, double *loss, void *stream) {
-    if (!n || !x || nt < 1 || !vox || !tgt || !wt || !(lr > 0.f)) return BEMFFT_EINVAL;
+    if (!n || !x || nt < 1 || nt > kMaxTargets || !vox || !tgt || !wt || !(lr > 0.f)) {
+        set_error("net_train_step: null argument, target count outside [1, 2^24] or lr <= 0");
+        return BEMFFT_EINVAL;
+    }
     hipStream_t st = (hipStream_t)stream;
     BF_CHECK(gradients(n, x, nt, vox, tgt, wt, loss, st));
     n->t += 1;
