@@ -167,46 +167,52 @@ struct RowCfg {
 
 template <typename R, int PX, int KIND>
 __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
+    // one block per long row: every thread places whole cells (all fields of
+    // a node at once, one round of gathers), then each wavefront transforms
+    // its pencils; fields beyond one block's pencils take further passes
     using Cfg = RowCfg<R, PX, KIND>;
-    constexpr int TPP = Cfg::TPP, PPB = Cfg::PPB, E = PX / TPP, PS = pstride<PX>();
+    constexpr int TPP = Cfg::TPP, NPEN = Cfg::PPB, E = PX / TPP, PS = pstride<PX>();
     constexpr int F = Terms<KIND>::F;
-    __shared__ cx<R> buf[PPB * PS];
+    const int d = bx;
+    if (d >= a.nd) return;  // block-uniform: batched members with fewer long rows
+    __shared__ cx<R> buf[NPEN * PS];
     __shared__ cx<R> tw[PX];
     const int tid = threadIdx.x;
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
     for (int i = tid; i < PX; i += 256) tw[i] = gtwx[i];
+    const int row = a.dense_rows[d];
+    const int s0 = a.rowptr[row], s1 = a.rowptr[row + 1];
     const int pen = tid / TPP, t = tid % TPP;
-    const int pid = bx * PPB + pen;  // (dense row, field)
-    const int d = pid / F, f = pid % F;
-    const bool live = d < a.nd;
     cx<R> *pb = buf + pen * PS;
+    cx<R> *Xd = static_cast<cx<R> *>(a.Xd);
+    for (int f0 = 0; f0 < F; f0 += NPEN) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) pb[pslot(t + e * TPP)] = {R(0), R(0)};
-    wave_lds_sync();
-    if (live) {
-        const int row = a.dense_rows[d];
-        const int s0 = a.rowptr[row], s1 = a.rowptr[row + 1];
-        for (int s = s0 + t; s < s1; s += TPP) {
+        for (int e = 0; e < E; ++e) pb[pslot(t + e * TPP)] = {R(0), R(0)};
+        __syncthreads();
+        for (int s = s0 + tid; s < s1; s += 256) {
             const int x = a.gx[s];
             if (s > s0 && a.gx[s - 1] == x) continue;  // summed by the first node of the cell
-            R v = field_value<R, KIND>(a, s, f);
-            for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) v += field_value<R, KIND>(a, s2, f);
-            pb[pslot(x)] = {v, R(0)};
+            for (int fl = 0; fl < NPEN && f0 + fl < F; ++fl) {
+                const int f = f0 + fl;
+                R v = field_value<R, KIND>(a, s, f);
+                for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) v += field_value<R, KIND>(a, s2, f);
+                buf[fl * PS + pslot(x)] = {v, R(0)};
+            }
         }
-    }
-    __syncthreads();  // twiddle table
-    cx<R> xr[E];
-    wave_lds_sync();
+        __syncthreads();
+        const int f = f0 + pen;
+        cx<R> xr[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) xr[e] = pb[pslot(t + e * TPP)];
-    fft_regs<R, PX, -1>(xr, pb, tw, t);
-    if (live) {
-        cx<R> *Xd = static_cast<cx<R> *>(a.Xd);
+        for (int e = 0; e < E; ++e) xr[e] = pb[pslot(t + e * TPP)];
+        fft_regs<R, PX, -1>(xr, pb, tw, t);
+        if (f < F) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int kx = t + e * TPP;
-            if (kx < a.hx) Xd[((size_t)d * F + f) * a.hx + kx] = xr[e];
+            for (int e = 0; e < E; ++e) {
+                const int kx = t + e * TPP;
+                if (kx < a.hx) Xd[((size_t)d * F + f) * a.hx + kx] = xr[e];
+            }
         }
+        __syncthreads();  // the next pass rewrites the pencils
     }
 }
 
@@ -698,7 +704,7 @@ struct Launch {
     template <int P> static int rows(const ApplyArgs &a, hipStream_t st) {
         using Cfg = RowCfg<R, P, KIND>;
         const int nfb = (a.m + 255) / 256;
-        const int nrb = (Terms<KIND>::F * a.nd + Cfg::PPB - 1) / Cfg::PPB;
+        const int nrb = a.nd;  // one block per long row
         hipLaunchKernelGGL((k_fields_rows<R, P, KIND>), dim3(nfb + nrb), dim3(256), 0, st, a, nfb);
         BF_HIP(hipGetLastError());
         return 0;
@@ -743,7 +749,7 @@ struct Launch {
     }
     template <int P> static int brows(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
         using Cfg = RowCfg<R, P, KIND>;
-        dim3 grid((Terms<KIND>::F * g.max_nd + Cfg::PPB - 1) / Cfg::PPB, 1, g.nmem);
+        dim3 grid(g.max_nd, 1, g.nmem);  // one block per long row
         hipLaunchKernelGGL((kb_rows_fft<R, P, KIND>), grid, dim3(256), 0, st, dm, io, 1);
         BF_HIP(hipGetLastError());
         return 0;
