@@ -184,8 +184,10 @@ typedef struct {
  * (iterative refinement); the returned true_relres is then the FP64 one.
  * Returns 0, ENOCONV (maxit reached; x and info still written), EBREAKDOWN
  * (non-finite values), EINVAL (also: refine on a plan without the FP64
- * operator), EDEVICE.  Synchronises 'stream' once per iteration (the
- * convergence scalar crosses to the host).
+ * operator), EDEVICE.  The host waits once per iteration for that
+ * iteration's Hessenberg column (the next iteration is already queued on
+ * 'stream', so the GPU does not idle meanwhile); the stream is synchronised
+ * before the call returns.
  */
 int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
                  const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
