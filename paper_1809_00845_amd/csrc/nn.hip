@@ -380,17 +380,39 @@ __global__ __launch_bounds__(256) void k_conv16(const _Float16 *__restrict__ in,
         f4 acc[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+        // For each (dy, dz) row only the centre tap is loaded; the dx = -1 and
+        // +1 taps are the centre values of the lanes d to the left and right
+        // (the tile's 16 voxels are consecutive, so within one grid row lane
+        // j - d holds voxel v - d), fetched by lane shuffles.  Lanes whose
+        // neighbour lies outside the tile load it; neighbours outside the
+        // grid row are zero padding.
+        const int xl = x - d, xr = x + d;
+        const int srcl = (lane - d) & 63, srcr = (lane + d) & 63;
 #pragma unroll
-        for (int t9 = 0; t9 < 9; ++t9) {
-            const int xx = x + d * (t9 % 3 - 1), y2 = yy + d * (t9 / 3 - 1);
-            const bool row_in = valid && xx >= 0 && xx < G && y2 >= 0 && y2 < G;
+        for (int r = 0; r < 3; ++r) {  // dy = r - 1
+            const int y2 = yy + d * (r - 1);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int zz = z + d * (q - 1);
-                h4 b = zero;
-                if (row_in && zz >= 0 && zz < G)
-                    b = *reinterpret_cast<const h4 *>(in + (((int64_t)zz * G + y2) * G + xx) * 16 + 4 * kq);
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + t9], b, acc[q], 0, 0, 0);
+                const bool row_ok = valid && y2 >= 0 && y2 < G && zz >= 0 && zz < G;
+                const _Float16 *rowp = in + (((int64_t)zz * G + y2) * G) * 16 + 4 * kq;
+                h4 bc = zero;
+                if (row_ok) bc = *reinterpret_cast<const h4 *>(rowp + (int64_t)x * 16);
+                double cbits;
+                __builtin_memcpy(&cbits, &bc, 8);
+                const double lbits = __shfl(cbits, srcl, 64), rbits = __shfl(cbits, srcr, 64);
+                h4 b_left = zero, b_right = zero;
+                if (row_ok && xl >= 0) {
+                    if (j >= d) __builtin_memcpy(&b_left, &lbits, 8);
+                    else b_left = *reinterpret_cast<const h4 *>(rowp + (int64_t)xl * 16);
+                }
+                if (row_ok && xr < G) {
+                    if (j + d < 16) __builtin_memcpy(&b_right, &rbits, 8);
+                    else b_right = *reinterpret_cast<const h4 *>(rowp + (int64_t)xr * 16);
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + r * 3 + 0], b_left, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + r * 3 + 1], bc, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + r * 3 + 2], b_right, acc[q], 0, 0, 0);
             }
         }
         if (valid) {
