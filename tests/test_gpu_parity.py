@@ -375,9 +375,10 @@ def test_navier_refined_solve(dev):
     assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
 
 
-@pytest.mark.parametrize("n", [16, 32, 48, 64, 96, 128, 160, 192])
+@pytest.mark.parametrize("n", [16, 32, 48, 64, 96, 128, 160, 192, 256])
 def test_every_fft_length_both_schedules(dev, n):
-    """Sphere on n^3 (padded 2n: every compiled FFT length up to 384), FP32,
+    """Sphere on n^3 (padded 2n: every compiled FFT length, up to the largest,
+    512), FP32,
     with the default and the alternative z schedule; oracle on a contiguous
     sample of 300 targets."""
     g = I.sphere3d(n, 0.35)
