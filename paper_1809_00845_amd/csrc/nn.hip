@@ -5,12 +5,14 @@
 // Input: voxel channels on the plan's grid, nonzero only at boundary nodes:
 // a = w/h^2, a n_x, a n_y, a n_z, a s u and a s b, with s = 1/rms(u) over
 // the Dirichlet nodes and b the right-hand side of the solve (minus the
-// operator applied to the known values, one application of eq. 16).  Layers: 3x3x3 convolutions with dilations d_l (zero
-// padding), ReLU between layers, one output channel read back at the node
-// voxels as s h q.  Storage and arithmetic are FP32.  Training minimises the
-// weighted squared error sum_j w_j (y(v_j) - s q_j)^2 / sum_j w_j against
-// solved problems (targets s h q_j), with Adam.  The solve keeps the guess only when its
-// residual is smaller than ||b|| (plain GMRES from zero otherwise).
+// operator applied to the known values, one application of eq. 16).
+// Layers: 3x3x3 convolutions with dilations d_l (zero padding), ReLU between
+// layers, one output channel read back at the node voxels as s h q.
+// Training (FP32 storage and arithmetic) minimises the weighted squared error
+// sum_j wt_j (y(v_j) - s h q_j)^2 against solved problems, with Adam.
+// Inference (the guess) runs in FP16 on the matrix cores with FP32
+// accumulation.  The solve keeps the guess only when its residual is smaller
+// than ||b|| (plain GMRES from zero otherwise).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
