@@ -457,6 +457,65 @@ def test_batch_apply_matches_single_plans(dev, use_graph):
     batch.close()
 
 
+@pytest.mark.parametrize("kind", ["navier", "laplace2d"])
+def test_batch_apply_other_kernels(dev, kind):
+    """Batches of Navier plans (3 components per node) and of 2D Laplace
+    plans: every member equals its own plan's apply bit for bit (graph
+    replayed twice), and one member matches the oracle."""
+    if kind == "navier":
+        geoms = [I.sphere3d(12, 0.35), I.sphere3d(16, 0.3), I.cube3d(12, 8)]
+        kern, okern, nc, prec = B.NAVIER3D, O.NAVIER3D, 3, B.FP64
+    else:
+        geoms = [I.circle2d(32, 0.4), I.circle2d(48, 0.3), I.square2d(40, 30)]
+        kern, okern, nc, prec = B.LAPLACE2D, O.LAPLACE2D, 1, B.FP64
+    plans = [B.Plan(g, kern, precision=prec) for g in geoms]
+    nrhs = 2
+    batch = B.Batch(plans, nrhs=nrhs, use_graph=True)
+    rng = np.random.default_rng(17)
+    qs, us = [], []
+    for g in geoms:
+        for _ in range(nrhs):
+            qs.append(rng.uniform(-1, 1, nc * g.m))
+            us.append(rng.uniform(-1, 1, nc * g.m))
+    q, u = np.concatenate(qs), np.concatenate(us)
+    qd, ud = _t(q, dev), _t(u, dev)
+    ref = []
+    k = 0
+    for p in plans:
+        for _ in range(nrhs):
+            o, n = batch.offsets[k], batch.lengths[k]
+            ref.append(p.apply(qd[o:o + n].contiguous(), ud[o:o + n].contiguous()).cpu().numpy())
+            k += 1
+    ref = np.concatenate(ref)
+    for rep in range(2):
+        r = torch.full_like(qd, float("nan"))
+        batch.apply(qd, ud, r)
+        torch.cuda.synchronize()
+        assert np.array_equal(r.cpu().numpy(), ref), rep
+        _ = (qd * 3.0).sum().item()
+    o, n = batch.offsets[2], batch.lengths[2]
+    g = geoms[1]
+    pr = O.problem(g, okern)
+    rr, sc = O.apply(pr, q[o:o + n].reshape(nc, -1) if nc > 1 else q[o:o + n],
+                     u[o:o + n].reshape(nc, -1) if nc > 1 else u[o:o + n], with_scale=True)
+    assert np.abs(ref[o:o + n] - np.reshape(rr, -1)).max() / np.max(sc) < TOL[prec]
+    batch.close()
+
+
+def test_solve_with_half_free_term(dev):
+    """Mixed sphere problem with the paper's c = 1/2 (C_HALF): the GMRES
+    solution equals the oracle's LU solution of the same (C_HALF) system."""
+    g = I.sphere3d(24, 0.35)
+    u, q = I.harmonic_3d_xyz(g)
+    bc = I.mixed_bc_upper(g)
+    known = np.where(bc == 0, u, q)
+    plan = B.Plan(g, B.LAPLACE3D, precision=B.FP64, c_mode=B.C_HALF)
+    x, info = plan.solve(_t(bc, dev), _t(known, dev), tol=1e-10)
+    assert info["status"] == 0 and info["true_relres"] <= 1e-10
+    xl = O.solve_lu(O.problem(g, O.LAPLACE3D), bc, known, cmode=O.C_HALF)
+    assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
+
+
 def test_batch_solve_matches_single_solves(dev):
     """Batched lockstep GMRES on mixed problems (Dirichlet above the centre,
     harmonic data of degree <= 3): every member takes the same iterations as
