@@ -116,6 +116,45 @@ def test_net_infer_fp16_matches_oracle(dev, G, dil):
     net.close()
 
 
+def test_net_full_size_sampled(dev):
+    """The bench's network on its 96^3 grid (dilations 1, 2, 4, 8), FP32
+    forward and FP16 inference, at sampled voxels (grid corners, faces and
+    interior).  The receptive field is +-15 voxels (1 + 2 + 4 + 8), so the
+    oracle evaluates each sampled voxel exactly on a 31^3 window of the grid
+    that holds it: the window is centred on the voxel except where it would
+    leave the grid, where it is shifted inwards so that its edge is the grid's
+    edge (the network zero-pads every layer there, as the oracle does at the
+    window's edge)."""
+    G, dil, R = 96, (1, 2, 4, 8), 15
+    W = 2 * R + 1
+    net = B.Net(G, dil, seed=5)
+    p = _rand_params(net, 31, scale=0.15)
+    x = _sparse_input(G, 32, frac=0.02)
+    xt = torch.tensor(x, device=dev)
+    y32 = torch.empty(G ** 3, dtype=torch.float32, device=dev)
+    y16 = torch.empty(G ** 3, dtype=torch.float32, device=dev)
+    net.forward(xt, y32)
+    net.infer(xt, y16)
+    torch.cuda.synchronize()
+    y32, y16 = y32.cpu().numpy(), y16.cpu().numpy()
+    x4 = x.astype(np.float64).reshape(6, G, G, G)
+    pts = [(0, 0, 0), (G - 1, G - 1, G - 1), (0, 47, 95), (48, 48, 48), (10, 90, 30), (95, 3, 60), (33, 66, 7)]
+    refs, g32, g16 = [], [], []
+    for c in pts:
+        st = [min(max(ci - R, 0), G - W) for ci in c]
+        crop = x4[:, st[0]:st[0] + W, st[1]:st[1] + W, st[2]:st[2] + W]
+        yc = NN.forward(p, list(dil), crop)[0]
+        refs.append(yc[c[0] - st[0], c[1] - st[1], c[2] - st[2]])
+        v = (c[0] * G + c[1]) * G + c[2]
+        g32.append(y32[v])
+        g16.append(y16[v])
+    refs, g32, g16 = map(np.asarray, (refs, g32, g16))
+    scale = np.abs(refs).max()
+    assert np.abs(g32 - refs).max() <= 1e-5 * scale
+    assert np.abs(g16 - refs).max() <= 1e-2 * scale
+    net.close()
+
+
 @pytest.mark.parametrize("G,dil", [(10, (1, 2, 4, 8)), (23, (1, 2, 4, 8)), (12, (1, 3)), (17, (2, 1, 1))])
 def test_net_gradients_match_oracle(dev, G, dil):
     net = B.Net(G, dil, seed=2)

@@ -516,6 +516,38 @@ def test_solve_with_half_free_term(dev):
     assert np.linalg.norm(x.cpu().numpy() - xl) / np.linalg.norm(xl) < 1e-6
 
 
+def test_config4_batched_full_size_sampled(dev):
+    """The 64-shape batch of the bench (seed 2, grids 64-160, 4 right-hand
+    sides, FP32, autotuned, graph replay): three members, on three grid
+    sizes, against the oracle on a contiguous sample of targets."""
+    items = I.draw_batch(2, 64)
+    geoms = I.star_batch(items)
+    plans = [B.Plan(g, B.LAPLACE3D, precision=B.FP32, autotune=1) for g in geoms]
+    nrhs = 4
+    batch = B.Batch(plans, nrhs=nrhs, use_graph=True)
+    q, u = _mixed_batch_inputs(geoms, nrhs, 21)
+    qd, ud = _t(q, dev), _t(u, dev)
+    r = torch.empty_like(qd)
+    batch.apply(qd, ud, r)
+    batch.apply(qd, ud, r)
+    torch.cuda.synchronize()
+    got = r.cpu().numpy()
+    seen = set()
+    for k in range(len(batch.offsets)):
+        gi = k // nrhs
+        n_grid = items[gi][0]
+        if n_grid in seen or len(seen) == 3:
+            continue
+        seen.add(n_grid)
+        o, n = batch.offsets[k], batch.lengths[k]
+        t0, t1 = n // 2, min(n, n // 2 + 200)
+        p = O.problem(geoms[gi], O.LAPLACE3D)
+        rr, sc = O.apply(p, q[o:o + n], u[o:o + n], targets=(t0, t1), with_scale=True)
+        assert np.abs(got[o + t0:o + t1] - rr).max() / sc.max() < TOL[B.FP32], (k, n_grid)
+    assert len(seen) == 3
+    batch.close()
+
+
 def test_batch_solve_matches_single_solves(dev):
     """Batched lockstep GMRES on mixed problems (Dirichlet above the centre,
     harmonic data of degree <= 3): every member takes the same iterations as
