@@ -297,6 +297,52 @@ int orc_apply(int kernel, double nu, double mu, double h, long m, const long *gr
 }
 
 /*
+ * The representation formula away from the nodes (eq. 4 / eq. 8 with the
+ * free term c = 1 for points inside the boundary and c = 0 outside, Sec. 2):
+ *
+ *     v(p) = S[q](p) - D[u](p) = sum_k G(p_k - p) w_k q_k - H(p_k - p; n_k) w_k u_k
+ *
+ * at arbitrary grid points p = origin + h g (Sec. 4: the inverse transform
+ * gives the convolution on the whole grid, not only at the nodes).  Inside
+ * a closed boundary carrying a consistent pair (u, q) this is the field u(p);
+ * outside it is 0.  A node k whose grid point coincides with p enters with
+ * the grid's value at offset 0 (single layer) and 0 (double layer) -- the
+ * plain grid sum, without the free term or the exact self term of the apply.
+ *
+ * pts: [npts][dim] grid indices of the targets.  out: [ncomp][npts].
+ */
+int orc_volume(int kernel, double nu, double mu, double h, long m, const long *grid_index,
+               const double *normals, const double *weights, const double *q, const double *u,
+               long npts, const long *pts, double *out)
+{
+    int dim = dim_of(kernel);
+    int nc = ncomp_of(kernel);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long t = 0; t < npts; ++t) {
+        double acc[3] = {0, 0, 0};
+        const long *gt = pts + t * dim;
+        for (long k = 0; k < m; ++k) {
+            const long *gk = grid_index + k * dim;
+            double xi[3] = {0, 0, 0};
+            int same_cell = 1;
+            for (int a = 0; a < dim; ++a) {
+                long d = gk[a] - gt[a];
+                xi[a] = h * (double)d;
+                if (d != 0) same_cell = 0;
+            }
+            double G[9], H[9];
+            single_block(kernel, nu, mu, h, xi, same_cell, 0, weights[k], normals + k * dim, G);
+            double_block(kernel, nu, xi, same_cell, weights[k], normals + k * dim, H);
+            for (int a = 0; a < nc; ++a)
+                for (int b = 0; b < nc; ++b)
+                    acc[a] += G[a * nc + b] * q[b * m + k] - H[a * nc + b] * u[b * m + k];
+        }
+        for (int a = 0; a < nc; ++a) out[a * npts + t] = acc[a];
+    }
+    return 0;
+}
+
+/*
  * Dense matrices of the discrete operator for small problems:
  * S and D are (nc*m) x (nc*m), row/column index = component * m + node, so
  * that r = C u + D u - S q with SoA vectors.  C (implicit) is returned in
