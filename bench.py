@@ -79,6 +79,35 @@ def zpass_alu_view(info, ms):
     return {"flops": flops, "achieved_tflops": tf, "peak_tflops_unpacked_fp32": 78.65, "frac": tf / 78.65}
 
 
+def bench_grid_eval(plan, q, u, info, front_ms, steps):
+    """S[q] - D[u] over the whole grid box (the representation formula
+    inside the boundary), FP64 out.  The evaluation shares the apply's
+    forward passes and z pass; its own stages are the inverse y transform
+    to a kx-contiguous buffer and the inverse x transforms of two rows per
+    pencil.  Their algorithmic bytes: read O g, write O Hx ny nzo complex;
+    read that back, write O nx ny nzo doubles."""
+    import torch
+
+    out = None
+    for _ in range(3):
+        out = plan.eval_grid(q, u, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.eval_grid(q, u, out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    px, py, _ = info["pad"]
+    nx, ny = info["n"][0], info["n"][1]
+    hx, nzo, O = px // 2 + 1, info["z_count"], info["noutputs"]
+    cb = 8  # FP32 complex
+    tail_bytes = O * hx * nzo * py * cb + 2 * O * hx * ny * nzo * cb + O * nx * ny * nzo * 8
+    tail_ms = ms - front_ms
+    return {"ms_per_eval": ms, "grid_points": nx * ny * nzo, "points_per_s": nx * ny * nzo * O / (ms * 1e-3),
+            "tail_ms": tail_ms, "tail_bytes": tail_bytes,
+            "tail_gbs": tail_bytes / (tail_ms * 1e-3) / 1e9 if tail_ms > 0 else None}
+
+
 def timed_applies(plan, q, u, r, steps, warmup):
     import torch
 
@@ -340,6 +369,8 @@ def main():
     ap.add_argument("--no-navier", action="store_true", help="skip the 192^3 Navier star workload")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the mixed cube solves to 1e-6 (FP64 and FP32 plans), 3 each (for profilers)")
+    ap.add_argument("--grid-eval-only", action="store_true",
+                    help="only the grid-box evaluation on the FP32 cube plan (for profilers)")
     ap.add_argument("--learned", action="store_true",
                     help="only the learned-start workload: train on GPU-solved star problems, then compare solves")
     ap.add_argument("--learned-grid", type=int, default=96)
@@ -406,6 +437,11 @@ def main():
 
     plan = B.Plan(cube, B.LAPLACE3D, precision=B.FP32, keep_fp64=True, autotune=1)
     info = plan.info()
+    if args.grid_eval_only:
+        sm = B.bemfft_apply_profile(plan.handle, q, u, r, reps=20)
+        print(json.dumps({"workload": "laplace3d cube 128^3 grid-box evaluation, fp32",
+                          **bench_grid_eval(plan, q, u, info, sm[0] + sm[1], args.steps)}), flush=True)
+        return
     dt = timed_applies(plan, q, u, r, args.steps, args.warmup)
     value = args.steps / dt
     stage_ms = B.bemfft_apply_profile(plan.handle, q, u, r, reps=max(20, args.steps // 4))
@@ -440,6 +476,9 @@ def main():
     }
     if not args.quick:
         extra = {}
+        # the field over the grid box (representation formula), same plan
+        extra["cube_grid_eval_fp32"] = bench_grid_eval(plan, q, u, info, stage_ms[0] + stage_ms[1],
+                                                       max(20, args.steps // 4))
         # FP64 apply, same cube
         plan64 = B.Plan(cube, B.LAPLACE3D, precision=B.FP64, autotune=1)
         dt64 = timed_applies(plan64, q, u, r, max(20, args.steps // 4), 5)

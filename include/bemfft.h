@@ -229,6 +229,28 @@ int bemfft_batch_members(const bemfft_batch *b, int64_t *offsets, int64_t *lengt
 
 int bemfft_batch_destroy(bemfft_batch *b);
 
+/* The field over the grid box: the representation formula of eq. (4) /
+ * eq. (8) with the free term c = 1 inside the boundary and c = 0 outside
+ * (Sec. 2), evaluated through the same convolution as bemfft_apply, whose
+ * inverse transform holds it at every grid point (Sec. 4):
+ *
+ *     out[o][z - z_lo][y][x] = S[q](p) - D[u](p),  p = origin + h (x, y, z),
+ *
+ * for 0 <= x < n[0], 0 <= y < n[1] and the planes z_lo <= z < z_lo + z_count
+ * that hold nodes (bemfft_plan_get_info; 2D: one plane).  Every point
+ * inside the boundary lies in this box.  Inside, for a pair (u, q) that
+ * solves the boundary problem, the value is the solution u(p); outside it
+ * is 0 up to discretisation error.  At grid points that hold nodes it is
+ * the plain grid sum (no free term, the grid's own value at offset 0 for
+ * the single layer): use bemfft_apply for values on the boundary.
+ *
+ * q, u: device, [ncomp][m] as in bemfft_apply.  out: device, ncomp *
+ * z_count * n[1] * n[0] doubles, x fastest.  Computed in the plan's working
+ * precision; async on `stream`; uses the plan's workspace, so it must not
+ * overlap other calls on the same plan.  Errors: EINVAL (null pointer),
+ * EDEVICE. */
+int bemfft_eval_grid(bemfft_plan *p, const double *q, const double *u, double *out, void *stream);
+
 /* Facts about a plan (host copies). */
 typedef struct {
     int dim, kernel, precision, c_mode;

@@ -67,7 +67,7 @@ def lib():
         L.orc_assemble.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_long, lp, dp, dp, dp, dp, dp]
         L.orc_volume.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_long, lp, dp, dp, dp, dp, ctypes.c_long, lp, dp]
+                                 ctypes.c_long, lp, dp, dp, dp, dp, ctypes.c_long, lp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -220,20 +220,23 @@ def apply(p: Problem, q, u, cmode=C_IMPLICIT, cuser=None, targets=None, with_sca
     return out[0] if len(out) == 1 else tuple(out)
 
 
-def volume(p: Problem, q, u, pts):
+def volume(p: Problem, q, u, pts, with_scale=False):
     """The representation formula at grid points (c = 1 inside, 0 outside):
     v(p) = S[q](p) - D[u](p), the plain grid sum at points that hold nodes.
     ``pts``: (npts, dim) integer grid indices.  Returns (ncomp, npts), or
-    (npts,) for Laplace."""
+    (npts,) for Laplace; with_scale adds the sum of the terms' magnitudes."""
     g = snap(p)
     nc = p.ncomp
     q = np.ascontiguousarray(np.reshape(q, (nc, p.m)), dtype=np.float64)
     u = np.ascontiguousarray(np.reshape(u, (nc, p.m)), dtype=np.float64)
     pts = np.ascontiguousarray(np.reshape(pts, (-1, p.dim)), dtype=np.int64)
     out = np.zeros((nc, pts.shape[0]))
+    sc = np.zeros((nc, pts.shape[0]))
     lib().orc_volume(p.kernel, p.nu, p.mu, p.h, p.m, _l(g), _d(p.normals), _d(p.weights), _d(q), _d(u),
-                     pts.shape[0], _l(pts), _d(out))
-    return out if nc > 1 else out[0]
+                     pts.shape[0], _l(pts), _d(out), _d(sc))
+    if nc == 1:
+        out, sc = out[0], sc[0]
+    return (out, sc) if with_scale else out
 
 
 def assemble(p: Problem):

@@ -309,17 +309,19 @@ int orc_apply(int kernel, double nu, double mu, double h, long m, const long *gr
  * the grid's value at offset 0 (single layer) and 0 (double layer) -- the
  * plain grid sum, without the free term or the exact self term of the apply.
  *
- * pts: [npts][dim] grid indices of the targets.  out: [ncomp][npts].
+ * pts: [npts][dim] grid indices of the targets.  out, scale (optional):
+ * [ncomp][npts]; scale = sum |G w q| + |H w u|, the magnitude of the terms
+ * that cancel in v, for normwise tolerances.
  */
 int orc_volume(int kernel, double nu, double mu, double h, long m, const long *grid_index,
                const double *normals, const double *weights, const double *q, const double *u,
-               long npts, const long *pts, double *out)
+               long npts, const long *pts, double *out, double *scale)
 {
     int dim = dim_of(kernel);
     int nc = ncomp_of(kernel);
 #pragma omp parallel for schedule(dynamic, 16)
     for (long t = 0; t < npts; ++t) {
-        double acc[3] = {0, 0, 0};
+        double acc[3] = {0, 0, 0}, mag[3] = {0, 0, 0};
         const long *gt = pts + t * dim;
         for (long k = 0; k < m; ++k) {
             const long *gk = grid_index + k * dim;
@@ -334,10 +336,15 @@ int orc_volume(int kernel, double nu, double mu, double h, long m, const long *g
             single_block(kernel, nu, mu, h, xi, same_cell, 0, weights[k], normals + k * dim, G);
             double_block(kernel, nu, xi, same_cell, weights[k], normals + k * dim, H);
             for (int a = 0; a < nc; ++a)
-                for (int b = 0; b < nc; ++b)
+                for (int b = 0; b < nc; ++b) {
                     acc[a] += G[a * nc + b] * q[b * m + k] - H[a * nc + b] * u[b * m + k];
+                    mag[a] += fabs(G[a * nc + b] * q[b * m + k]) + fabs(H[a * nc + b] * u[b * m + k]);
+                }
         }
-        for (int a = 0; a < nc; ++a) out[a * npts + t] = acc[a];
+        for (int a = 0; a < nc; ++a) {
+            out[a * npts + t] = acc[a];
+            if (scale) scale[a * npts + t] = mag[a];
+        }
     }
     return 0;
 }

@@ -61,7 +61,7 @@ EXPORTS = [
     "bemfft_batch_members", "bemfft_batch_destroy", "bemfft_net_create", "bemfft_net_destroy",
     "bemfft_net_num_params", "bemfft_net_get_params", "bemfft_net_set_params", "bemfft_net_input",
     "bemfft_net_forward", "bemfft_net_infer", "bemfft_net_gradients", "bemfft_net_train_step", "bemfft_net_guess",
-    "bemfft_plan_node_voxels",
+    "bemfft_plan_node_voxels", "bemfft_eval_grid",
 ]
 
 _lib = None
@@ -86,6 +86,7 @@ def load():
                                      ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      ctypes.POINTER(bemfft_plan_opts)]
     L.bemfft_apply.argtypes = [vp, vp, vp, vp, vp]
+    L.bemfft_eval_grid.argtypes = [vp, vp, vp, vp, vp]
     L.bemfft_apply_profile.argtypes = [vp, vp, vp, vp, ctypes.c_int, dp, vp]
     L.bemfft_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(bemfft_solve_opts),
                                ctypes.POINTER(bemfft_solve_info), vp]
@@ -198,6 +199,11 @@ def bemfft_apply(plan, q, u, r, stream=None):
     return _check(load().bemfft_apply(plan, _ptr(q), _ptr(u), _ptr(r), _stream_ptr(stream)), "bemfft_apply")
 
 
+def bemfft_eval_grid(plan, q, u, out, stream=None):
+    return _check(load().bemfft_eval_grid(plan, _ptr(q), _ptr(u), _ptr(out), _stream_ptr(stream)),
+                  "bemfft_eval_grid")
+
+
 def bemfft_apply_profile(plan, q, u, r, reps=10, stream=None):
     """Mean per-stage milliseconds (fwd_xy, zpass, inv_yx, epilogue)."""
     ms = (ctypes.c_double * 4)()
@@ -266,6 +272,20 @@ class Plan:
             r = torch.empty_like(u)
         bemfft_apply(self.handle, q, u, r, stream)
         return r
+
+    def eval_grid(self, q, u, out=None, stream=None):
+        """S[q] - D[u] on the grid box [0, n0) x [0, n1) x [z_lo, z_lo + z_count):
+        shape (ncomp, z_count, n1, n0) in 3D, (n1, n0) in 2D."""
+        import torch
+
+        inf = self.info()
+        shape = (self.ncomp, inf["z_count"], inf["n"][1], inf["n"][0])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=u.device)
+        elif out.dtype != torch.float64 or out.numel() != int(np.prod(shape)):
+            raise ValueError(f"eval_grid: out needs {shape} float64 values")
+        bemfft_eval_grid(self.handle, q, u, out, stream)
+        return out[0, 0] if inf["dim"] == 2 else out
 
     def solve(self, bc, known, unknown=None, **kw):
         import torch

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "apply_impl.hpp"
+#include "volume_impl.hpp"
 #include "fft_device.hpp"
 #include "internal.hpp"
 #include "kinds.hpp"
@@ -629,6 +629,21 @@ int bemfft_apply_profile(bemfft_plan *p, const double *q, const double *u, doubl
     if (status == BEMFFT_EDEVICE) set_error("apply_profile: HIP failure");
     for (int k = 0; k < 4; ++k) stage_ms[k] = acc[k] / reps;
     return status;
+}
+
+int bemfft_eval_grid(bemfft_plan *p, const double *q, const double *u, double *out, void *stream) {
+    if (!p || !q || !u || !out) {
+        set_error("eval_grid: null argument");
+        return BEMFFT_EINVAL;
+    }
+    ApplyArgs a;
+    fill_apply_args(p, p->eng, p->eng, &a);
+    a.q = q;
+    a.u = u;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->kernel == 0) return volume_kind<0>(p->eng.precision, a, out, st, nullptr);
+    if (p->kernel == 1) return volume_kind<1>(p->eng.precision, a, out, st, nullptr);
+    return volume_kind<2>(p->eng.precision, a, out, st, nullptr);
 }
 
 int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {

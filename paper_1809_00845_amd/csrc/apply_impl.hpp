@@ -715,8 +715,9 @@ struct Launch {
     }
     template <int P> static int kxc(int) { return InvCfg<R, P, KIND>::KXC; }
 
-    // ev (optional): five events recorded around the four stages.
-    static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
+    // Fields, forward x/y and the z pass: everything up to Z.  ev (optional):
+    // events 0-2 recorded around the two stages.
+    static int front(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
         if (ev) BF_HIP(hipEventRecord(ev[0], st));
         if (a.nd > 0) {
             BF_CHECK(dispatch_rows(a, st));  // fields and long-row transforms, one launch
@@ -727,6 +728,12 @@ struct Launch {
         if (ev) BF_HIP(hipEventRecord(ev[1], st));
         BF_CHECK(dispatch_z(a, st));
         if (ev) BF_HIP(hipEventRecord(ev[2], st));
+        return 0;
+    }
+
+    // ev (optional): five events recorded around the four stages.
+    static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
+        BF_CHECK(front(a, st, ev));
         BF_CHECK(dispatch_inv(a, st));
         if (ev) BF_HIP(hipEventRecord(ev[3], st));
         hipLaunchKernelGGL((k_epilogue<Terms<KIND>::O>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);

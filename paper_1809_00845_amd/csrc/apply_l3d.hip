@@ -1,5 +1,5 @@
 // apply_l3d.hip -- instantiation of the hot path for kernel family 1.
-#include "apply_impl.hpp"
+#include "volume_impl.hpp"
 
 namespace bemfft {
 
@@ -19,6 +19,12 @@ template <>
 int apply_batch_kind<1>(int precision, const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
     if (precision == BEMFFT_FP32) return Launch<float, 1>::run_batch(dm, io, g, st);
     return Launch<double, 1>::run_batch(dm, io, g, st);
+}
+
+template <>
+int volume_kind<1>(int precision, const ApplyArgs &a, double *out, hipStream_t st, hipEvent_t *ev) {
+    if (precision == BEMFFT_FP32) return VolumeLaunch<float, 1>::run(a, out, st, ev);
+    return VolumeLaunch<double, 1>::run(a, out, st, ev);
 }
 
 }  // namespace bemfft

@@ -1,0 +1,183 @@
+// volume_impl.hpp -- the field over the whole grid box instead of at the
+// nodes only.  The representation formula (eq. 4 / eq. 8 with c = 1 for
+// points inside the boundary and c = 0 outside, Sec. 2) reads
+//     v(p) = S[q](p) - D[u](p),
+// and the inverse transform of the convolution gives it at every grid
+// point (Sec. 4), so the forward passes and the z pass of the apply are
+// reused unchanged and only the last stage differs:
+//
+//   k_vol_y  per occupied z-plane and chunk of kx: inverse y-FFT of every
+//            output, rows y < ny written with kx contiguous
+//                                                -> W[o][z][y][kx]  (in Y)
+//   k_vol_x  two grid rows per pencil: the half spectra of rows a and b are
+//            extended to Hermitian sequences A, B (imaginary parts at kx = 0
+//            and kx = Px/2 dropped, as the node gather does) and packed as
+//            A + iB; one inverse complex FFT of length Px then holds row a
+//            in its real and row b in its imaginary part.  x < nx is kept,
+//            negated (the grid holds D[u] - S[q]).
+//                                                -> out[o][z][y][x] (FP64)
+//
+// W reuses the forward intermediate Y, free once the z pass has run:
+// O nzo ny Hx <= F Hx nzo Py complex values.
+#pragma once
+
+#include "apply_impl.hpp"
+
+namespace bemfft {
+
+// ------------------------------------------------------------------ k_vol_y
+template <typename R, int PY, int KIND>
+struct VolYCfg {
+    static constexpr int O = Terms<KIND>::O;
+    static constexpr int TPP = PencilShape<PY>::TPP;
+    static constexpr int CB = (int)sizeof(cx<R>);
+    static constexpr int PS = pstride<PY>();
+    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - PY * CB) / (O * PS * CB)), 1, 16);
+    static constexpr int NT = O * KXC * TPP;
+};
+
+template <typename R, int PY, int KIND>
+__global__ __launch_bounds__((VolYCfg<R, PY, KIND>::NT)) void k_vol_y(ApplyArgs a) {
+    using Cfg = VolYCfg<R, PY, KIND>;
+    constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
+    __shared__ cx<R> buf[O * KXC * PS];
+    __shared__ cx<R> tw[PY];
+    const int tid = threadIdx.x;
+    const int kx0 = blockIdx.x * KXC;
+    const int zz = blockIdx.y;
+    const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
+    for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
+    const int pen = tid / TPP, t = tid % TPP;
+    const int o = pen / KXC, kx = kx0 + pen % KXC;
+    cx<R> x[E];
+    if (kx < a.hx) {
+        const cx<R> *Zr = static_cast<const cx<R> *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = Zr[t + e * TPP];
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = {R(0), R(0)};
+    }
+    __syncthreads();  // twiddle table
+    cx<R> *pb = buf + pen * PS;
+    fft_regs<R, PY, 1>(x, pb, tw, t);
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {  // ny <= Py/2: rows y >= Py/2 lie outside the box
+        const int y = t + e * TPP;
+        if (y < a.ny) pb[pslot(y)] = x[e];
+    }
+    __syncthreads();  // the transposed store reads every pencil
+    const int nk = min(KXC, a.hx - kx0);
+    cx<R> *W = static_cast<cx<R> *>(a.Y);
+    for (int i = tid; i < O * a.ny * KXC; i += NT) {
+        const int kl = i % KXC, rest = i / KXC;
+        const int y = rest % a.ny, oo = rest / a.ny;
+        if (kl < nk) W[((size_t)(oo * a.nzo + zz) * a.ny + y) * a.hx + kx0 + kl] = buf[(oo * KXC + kl) * PS + pslot(y)];
+    }
+}
+
+// ------------------------------------------------------------------ k_vol_x
+template <typename R, int PX>
+struct VolXCfg {
+    static constexpr int TPP = PencilShape<PX>::TPP;
+    static constexpr int CB = (int)sizeof(cx<R>);
+    static constexpr int PS = pstride<PX>();
+    static constexpr int PPB = clampi(mini(256 / TPP, (64 * 1024 - PX * CB) / (PS * CB)), 1, 64);
+    static constexpr int NT = PPB * TPP;
+};
+
+// W: [nrows][hx] half spectra; out: [nrows][nx].
+template <typename R, int PX>
+__global__ __launch_bounds__((VolXCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__restrict__ W, const cx<R> *twx,
+                                                                 int hx, int nx, int64_t nrows,
+                                                                 double *__restrict__ out) {
+    using Cfg = VolXCfg<R, PX>;
+    constexpr int TPP = Cfg::TPP, PS = Cfg::PS, PPB = Cfg::PPB, NT = Cfg::NT, E = PX / TPP;
+    __shared__ cx<R> buf[PPB * PS];
+    __shared__ cx<R> tw[PX];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < PX; i += NT) tw[i] = twx[i];
+    const int pen = tid / TPP, t = tid % TPP;
+    const int64_t ra = ((int64_t)blockIdx.x * PPB + pen) * 2, rb = ra + 1;
+    const bool va = ra < nrows, vb = rb < nrows;
+    const cx<R> *Wa = W + ra * hx, *Wb = W + rb * hx;
+    cx<R> x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * TPP;
+        const bool lo = 2 * k <= PX;
+        const int kk = lo ? k : PX - k;  // kk < hx
+        cx<R> A = va ? Wa[kk] : cx<R>{R(0), R(0)};
+        cx<R> B = vb ? Wb[kk] : cx<R>{R(0), R(0)};
+        if (kk == 0 || 2 * kk == PX) {
+            A.y = R(0);
+            B.y = R(0);
+        }
+        if (!lo) {  // Hermitian extension: conj of the mirrored coefficient
+            A.y = -A.y;
+            B.y = -B.y;
+        }
+        x[e] = {A.x - B.y, A.y + B.x};  // A + iB
+    }
+    __syncthreads();  // twiddle table
+    fft_regs<R, PX, 1>(x, buf + pen * PS, tw, t);
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {  // nx <= Px/2
+        const int xg = t + e * TPP;
+        if (xg < nx) {
+            if (va) out[ra * nx + xg] = -(double)x[e].x;
+            if (vb) out[rb * nx + xg] = -(double)x[e].y;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launcher
+template <typename R, int KIND>
+struct VolumeLaunch {
+    template <int P> static int y(const ApplyArgs &a, hipStream_t st) {
+        using Cfg = VolYCfg<R, P, KIND>;
+        dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
+        hipLaunchKernelGGL((k_vol_y<R, P, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    template <int P> static int x(const ApplyArgs &a, double *out, hipStream_t st) {
+        using Cfg = VolXCfg<R, P>;
+        const int64_t nrows = (int64_t)Terms<KIND>::O * a.nzo * a.ny;
+        const int64_t nb = (nrows + 2 * Cfg::PPB - 1) / (2 * Cfg::PPB);
+        hipLaunchKernelGGL((k_vol_x<R, P>), dim3((unsigned)nb), dim3(Cfg::NT), 0, st,
+                           static_cast<const cx<R> *>(a.Y), static_cast<const cx<R> *>(a.twx), a.hx, a.nx, nrows,
+                           out);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    static int dispatch_y(const ApplyArgs &a, hipStream_t st) {
+        BF_SIZE_SWITCH(a.py, y, a, st);
+        set_error("unsupported y length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    static int dispatch_x(const ApplyArgs &a, double *out, hipStream_t st) {
+        BF_SIZE_SWITCH(a.px, x, a, out, st);
+        set_error("unsupported x length");
+        return BEMFFT_EUNSUPPORTED;
+    }
+    // ev (optional): four events recorded around the three stages (front,
+    // inverse y, inverse x).
+    static int run(const ApplyArgs &a, double *out, hipStream_t st, hipEvent_t *ev) {
+        if (ev) BF_HIP(hipEventRecord(ev[0], st));
+        BF_CHECK((Launch<R, KIND>::front(a, st, nullptr)));
+        if (ev) BF_HIP(hipEventRecord(ev[1], st));
+        BF_CHECK(dispatch_y(a, st));
+        if (ev) BF_HIP(hipEventRecord(ev[2], st));
+        BF_CHECK(dispatch_x(a, out, st));
+        if (ev) BF_HIP(hipEventRecord(ev[3], st));
+        return 0;
+    }
+};
+
+// Per-family entry point, instantiated beside apply_kind.
+template <int KIND>
+int volume_kind(int precision, const ApplyArgs &a, double *out, hipStream_t st, hipEvent_t *ev);
+
+}  // namespace bemfft
