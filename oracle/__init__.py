@@ -290,3 +290,38 @@ def solve_lu(p: Problem, bc, known, cmode=C_IMPLICIT, cuser=None):
     A, b = mixed_system(p, bc, known, cmode, cuser)
     x = np.linalg.solve(A, b)
     return x.reshape(p.ncomp, p.m) if p.ncomp > 1 else x
+
+
+def dirichlet_cg(p: Problem, u, tol=1e-10, maxit=1000, precond=True, cmode=C_IMPLICIT, cuser=None, x0=None):
+    """The paper's solver (end of Sec. 4): conjugate gradients for q in
+    S q = c u + D u (eq. 4 with r = 0, u given everywhere, Laplace).
+
+    S = G W with G symmetric, so CG (Hestenes-Stiefel, with an optional
+    diagonal preconditioner) runs on the symmetrised matrix
+    A = W^1/2 S W^-1/2 and right-hand side W^1/2 (c u + D u); q = W^-1/2 y.
+    Stops when ||r|| <= tol ||b|| for the recursive residual r.  Returns
+    (q, iterations)."""
+    S, D, cimp = assemble(p)
+    C = c_matrix(p, cmode, cuser, cimp)
+    sw = np.sqrt(p.weights)
+    A = sw[:, None] * S / sw[None, :]
+    b = sw * ((C + D) @ np.reshape(u, -1))
+    minv = 1.0 / np.diag(A) if precond else np.ones(p.m)
+    y = np.zeros(p.m) if x0 is None else sw * np.reshape(x0, -1)
+    r = b - A @ y
+    z = minv * r
+    d = z.copy()
+    rz = r @ z
+    bn = np.linalg.norm(b)
+    it = 0
+    while np.linalg.norm(r) > tol * bn and it < maxit:
+        ad = A @ d
+        alpha = rz / (d @ ad)
+        y = y + alpha * d
+        r = r - alpha * ad
+        z = minv * r
+        rz_new = r @ z
+        d = z + (rz_new / rz) * d
+        rz = rz_new
+        it += 1
+    return y / sw, it
