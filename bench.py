@@ -108,6 +108,37 @@ def bench_grid_eval(plan, q, u, info, front_ms, steps):
             "tail_gbs": tail_bytes / (tail_ms * 1e-3) / 1e9 if tail_ms > 0 else None}
 
 
+def bench_dirichlet_cg(B, I, dev):
+    """The paper's solver (end of Sec. 4): CG on the symmetrised Dirichlet
+    single-layer system, against GMRES on the same problem, both FP64 to a
+    1e-6 relative residual.  The 2D square has 250 grid points per side on a
+    256^2 grid (the largest the 512-point transforms allow; the paper's
+    Fig. 6 uses 500); the sphere is the 128^3 one."""
+    import torch
+
+    res = {}
+    for name, g, kind, harm in (("square2d_250_per_side_256sq", I.square2d(256, 250), B.LAPLACE2D,
+                                 I.harmonic_2d_x2y2),
+                                ("sphere_128cubed", I.sphere3d(128, 0.35), B.LAPLACE3D, I.harmonic_3d_xyz)):
+        u = torch.tensor(harm(g)[0], device=dev)
+        plan = B.Plan(g, kind, precision=B.FP64)
+        bc = torch.zeros(g.m, dtype=torch.uint8, device=dev)
+        row = {"nodes": g.m}
+        for tag, fn in (("cg_jacobi", lambda: plan.solve_cg(u, tol=1e-6, precond=1)),
+                        ("cg_plain", lambda: plan.solve_cg(u, tol=1e-6, precond=0)),
+                        ("gmres_jacobi", lambda: plan.solve(bc, u, tol=1e-6))):
+            fn()  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf = fn()
+            torch.cuda.synchronize()
+            row[tag] = {"seconds": time.perf_counter() - t0, "iters": inf["iters"],
+                        "true_relres": inf["true_relres"], "status": inf["status"]}
+        plan.close()
+        res[name] = row
+    return res
+
+
 def timed_applies(plan, q, u, r, steps, warmup):
     import torch
 
@@ -369,6 +400,8 @@ def main():
     ap.add_argument("--no-navier", action="store_true", help="skip the 192^3 Navier star workload")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the mixed cube solves to 1e-6 (FP64 and FP32 plans), 3 each (for profilers)")
+    ap.add_argument("--cg-only", action="store_true",
+                    help="only the Dirichlet CG vs GMRES solves (2D square, 3D sphere)")
     ap.add_argument("--grid-eval-only", action="store_true",
                     help="only the grid-box evaluation on the FP32 cube plan (for profilers)")
     ap.add_argument("--learned", action="store_true",
@@ -406,6 +439,9 @@ def main():
         return
     if args.learned:
         print(json.dumps(bench_learned(B, args)), flush=True)
+        return
+    if args.cg_only:
+        print(json.dumps(bench_dirichlet_cg(B, I, dev)), flush=True)
         return
     if args.solve_only:
         g = I.cube3d(128, 100)
@@ -517,6 +553,7 @@ def main():
                                            "residual_precision": "fp64" if tag != "fp32" else "fp32",
                                            "status": si["status"]}
         extra["time_to_solve_1e-6"] = solves
+        extra["dirichlet_cg_vs_gmres"] = bench_dirichlet_cg(B, I, dev)
         extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
         if not args.no_navier:
             print("  navier star 192^3 ...", file=sys.stderr, flush=True)

@@ -192,6 +192,35 @@ typedef struct {
 int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
                  const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
 
+/*
+ * Dirichlet Laplace problem by conjugate gradients, the paper's own solver
+ * (end of Sec. 4): u given at every node, find q with
+ *     S[q] = c u + D[u]                      (eq. 4 with r = 0).
+ * S = G W, where G (the single-layer kernel on the grid, with the exact
+ * self terms on its diagonal) is symmetric and W = diag(w), so CG runs on
+ * the symmetrised system
+ *     W^1/2 G W^1/2 y = W^1/2 (c u + D[u]),  q = W^-1/2 y,
+ * which is positive definite for the 3D kernel and for the 2D kernel when
+ * the boundary's logarithmic capacity is below 1 (any boundary inside a
+ * disc of radius 1).  Each iteration is one apply in the plan's working
+ * precision; vectors and dot products are FP64.
+ *   u  device, [m]: the Dirichlet data.
+ *   q  device, [m]: on entry the initial guess if opts->use_x0 = 1; on
+ *      return the solution.
+ *   opts: tol (on ||r|| / ||b|| of the symmetrised system), maxit, precond
+ *      (0 none, 1 Jacobi with the exact self terms), use_x0 (0 or 1);
+ *      restart and the refinement fields are ignored.  NULL = defaults.
+ *   info: iters, true_relres (recomputed with a fresh apply), status,
+ *      seconds; the other fields are 0 (x0_relres -1).
+ * Returns 0, ENOCONV (maxit reached; q and info written), EBREAKDOWN (a
+ * direction with p.Ap <= 0: the system is not positive definite, q is not
+ * meaningful), EINVAL (Navier plan, null pointer, bad options), ENOMEM,
+ * EDEVICE.  Synchronises `stream`; not concurrent with other calls on the
+ * same plan.
+ */
+int bemfft_solve_cg(bemfft_plan *p, const double *u, double *q, const bemfft_solve_opts *opts,
+                    bemfft_solve_info *info, void *stream);
+
 /* ------------------------------------------------------------- batches
  * Many boundaries and right-hand sides at once (the operator of eq. 4 / 8
  * for each; nothing couples the members).  A member is (plan i, right-hand

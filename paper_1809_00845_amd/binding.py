@@ -61,7 +61,7 @@ EXPORTS = [
     "bemfft_batch_members", "bemfft_batch_destroy", "bemfft_net_create", "bemfft_net_destroy",
     "bemfft_net_num_params", "bemfft_net_get_params", "bemfft_net_set_params", "bemfft_net_input",
     "bemfft_net_forward", "bemfft_net_infer", "bemfft_net_gradients", "bemfft_net_train_step", "bemfft_net_guess",
-    "bemfft_plan_node_voxels", "bemfft_eval_grid",
+    "bemfft_plan_node_voxels", "bemfft_eval_grid", "bemfft_solve_cg",
 ]
 
 _lib = None
@@ -90,6 +90,8 @@ def load():
     L.bemfft_apply_profile.argtypes = [vp, vp, vp, vp, ctypes.c_int, dp, vp]
     L.bemfft_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(bemfft_solve_opts),
                                ctypes.POINTER(bemfft_solve_info), vp]
+    L.bemfft_solve_cg.argtypes = [vp, vp, vp, ctypes.POINTER(bemfft_solve_opts), ctypes.POINTER(bemfft_solve_info),
+                                  vp]
     L.bemfft_plan_get_info.argtypes = [vp, ctypes.POINTER(bemfft_plan_info)]
     L.bemfft_plan_get_c.argtypes = [vp, dp]
     L.bemfft_plan_destroy.argtypes = [vp]
@@ -224,6 +226,14 @@ def bemfft_solve(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, pr
             "x0_used": info.x0_used, "x0_relres": info.x0_relres}
 
 
+def bemfft_solve_cg(plan, u, q, tol=1e-6, maxit=1000, precond=1, use_x0=0, stream=None):
+    o = bemfft_solve_opts(tol, 100, maxit, precond, use_x0, 0, 1e-4, 20)
+    info = bemfft_solve_info()
+    st = load().bemfft_solve_cg(plan, _ptr(u), _ptr(q), ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+    _check(st, "bemfft_solve_cg")
+    return {"status": st, "iters": info.iters, "true_relres": info.true_relres, "seconds": info.seconds}
+
+
 def bemfft_plan_get_info(plan):
     info = bemfft_plan_info()
     _check(load().bemfft_plan_get_info(plan, ctypes.byref(info)), "bemfft_plan_get_info")
@@ -295,6 +305,17 @@ class Plan:
             kw.setdefault("use_x0", 0)
         info = bemfft_solve(self.handle, bc, known, unknown, **kw)
         return unknown, info
+
+    def solve_cg(self, u, q=None, **kw):
+        """Dirichlet Laplace problem by CG on the symmetrised single-layer
+        system: q with S[q] = c u + D[u]."""
+        import torch
+
+        if q is None:
+            q = torch.zeros_like(u, memory_format=torch.contiguous_format)
+            kw.setdefault("use_x0", 0)
+        info = bemfft_solve_cg(self.handle, u, q, **kw)
+        return q, info
 
     def info(self):
         return bemfft_plan_get_info(self.handle)

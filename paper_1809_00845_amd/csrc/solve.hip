@@ -396,6 +396,124 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
     return status;
 }
 
+// ------------------------------------------------------------------ CG
+// Conjugate gradients on the symmetrised Dirichlet single-layer system.
+// S = G W with G symmetric (the single-layer kernel is even, and the self
+// and same-cell values are symmetric), so A = W^1/2 S W^-1/2 = W^1/2 G W^1/2
+// is symmetric; it is positive definite for the 3D kernel and for the 2D
+// one when the boundary's logarithmic capacity is below 1.  Scalars stay on
+// the device: sc[4 c + 0] = r.z and sc[4 c + 1] = r.r of slot c (two slots,
+// alternating per iteration), sc[4 c + 2] = p.Ap of the step that read slot c.
+
+// sw[perm[s]] = sqrt(w[s]): the weights in the caller's node order
+__global__ void k_cg_sqrtw(const int *perm, const double *w, double *sw, int64_t m) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x)
+        sw[perm[s]] = sqrt(w[s]);
+}
+
+// apply inputs for S W^-1/2 v: q = v / sw, u = 0
+__global__ void k_cg_in(const double *v, const double *sw, double *q, double *u, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        q[i] = v[i] / sw[i];
+        u[i] = 0.0;
+    }
+}
+
+// y = a sw y (a = -1 turns apply(q, 0) = -S q into W^1/2 S q; a = 1 scales b)
+__global__ void k_cg_scale(double *y, const double *sw, double a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * sw[i] * y[i];
+}
+
+// dinv = 1 / d with d = -dneg (the positive diagonal of S); 1 where off or
+// where d is not positive and finite
+__global__ void k_cg_diag(const double *dneg, double *dinv, int64_t n, int on) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = -dneg[i];
+        dinv[i] = (on && d > 0.0 && isfinite(d)) ? 1.0 / d : 1.0;
+    }
+}
+
+// r = b - Av (or b if Av is null); z = dinv r; p = z; per-block partial
+// sums of r.z and r.r into partial[blk][2]
+__global__ __launch_bounds__(256) void k_cg_init(const double *b, const double *av, const double *dinv, double *r,
+                                                 double *z, double *pv, int64_t n, double *partial) {
+    __shared__ double sm[4][2];
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ri = av ? b[i] - av[i] : b[i];
+        const double zi = dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        pv[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        rz += __shfl_xor(rz, off, 64);
+        rr += __shfl_xor(rr, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) {
+        sm[threadIdx.x / 64][0] = rz;
+        sm[threadIdx.x / 64][1] = rr;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        partial[(int64_t)blockIdx.x * 2 + threadIdx.x] =
+            (sm[0][threadIdx.x] + sm[1][threadIdx.x]) + (sm[2][threadIdx.x] + sm[3][threadIdx.x]);
+}
+
+// alpha = r.z / p.Ap of slot cur; x += alpha p; r -= alpha Ap; z = dinv r;
+// partial sums of the new r.z and r.r (fixed order: reproducible)
+__global__ __launch_bounds__(256) void k_cg_step(const double *sc, int cur, double *x, double *r, double *z,
+                                                 const double *pv, const double *ap, const double *dinv, int64_t n,
+                                                 double *partial) {
+    __shared__ double sm[4][2];
+    const double alpha = sc[4 * cur] / sc[4 * cur + 2];
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * pv[i];
+        const double ri = r[i] - alpha * ap[i];
+        const double zi = dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        rz += __shfl_xor(rz, off, 64);
+        rr += __shfl_xor(rr, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) {
+        sm[threadIdx.x / 64][0] = rz;
+        sm[threadIdx.x / 64][1] = rr;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        partial[(int64_t)blockIdx.x * 2 + threadIdx.x] =
+            (sm[0][threadIdx.x] + sm[1][threadIdx.x]) + (sm[2][threadIdx.x] + sm[3][threadIdx.x]);
+}
+
+// p = z + beta p with beta = (r.z of slot nxt) / (r.z of slot cur)
+__global__ void k_cg_dir(const double *sc, int cur, double *pv, const double *z, int64_t n) {
+    const double beta = sc[4 * (cur ^ 1)] / sc[4 * cur];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pv[i] = z[i] + beta * pv[i];
+}
+
+// Av = W^1/2 S W^-1/2 v through one apply of the plan's working precision
+int cg_op(bemfft_plan *p, const double *v, const double *sw, Ws &ws, double *av, hipStream_t st) {
+    const int64_t n = p->m;
+    hipLaunchKernelGGL(k_cg_in, dim3(grid_for(n)), dim3(256), 0, st, v, sw, ws.q, ws.u, n);
+    BF_HIP(hipGetLastError());
+    BF_CHECK(launch_apply(p, p->eng, ws.q, ws.u, av, st));
+    hipLaunchKernelGGL(k_cg_scale, dim3(grid_for(n)), dim3(256), 0, st, av, sw, -1.0, n);
+    BF_HIP(hipGetLastError());
+    return 0;
+}
+
 }  // namespace
 }  // namespace bemfft
 
@@ -517,6 +635,118 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
         info->applies64 = o.refine ? applies64 : 0;
         info->x0_used = use_x0 ? 1 : 0;
         info->x0_relres = o.use_x0 == 2 ? rel0 : -1.0;
+    }
+    return status;
+}
+
+extern "C" int bemfft_solve_cg(bemfft_plan *p, const double *u, double *q, const bemfft_solve_opts *opts,
+                               bemfft_solve_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !u || !q) {
+        set_error("solve_cg: null argument");
+        return BEMFFT_EINVAL;
+    }
+    if (p->kernel == BEMFFT_NAVIER3D) {
+        set_error("solve_cg: Laplace plans only");
+        return BEMFFT_EINVAL;
+    }
+    bemfft_solve_opts o{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0) || o.maxit < 1 || o.use_x0 < 0 || o.use_x0 > 1 || o.precond < 0 || o.precond > 1) {
+        set_error("solve_cg: bad options");
+        return BEMFFT_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = p->m;
+    Ws ws{};
+    BF_CHECK(ensure_workspace(p, 1, ws));
+    double *hp = p->h_pinned;
+    double *sc = ws.hd;  // device scalars
+    double *sw = ws.V, *b = ws.b, *x = ws.x, *r = ws.r, *z = ws.ro, *pv = ws.d, *ap = ws.w, *dinv = ws.dinv;
+    hipLaunchKernelGGL(k_cg_sqrtw, dim3(grid_for(n)), dim3(256), 0, st, p->d_perm, p->d_w, sw, n);
+    BF_HIP(hipGetLastError());
+    // b = W^1/2 (c u + D[u]) = W^1/2 apply(0, u)
+    BF_HIP(hipMemsetAsync(ws.q, 0, n * sizeof(double), st));
+    BF_CHECK(launch_apply(p, p->eng, ws.q, u, b, st));
+    hipLaunchKernelGGL(k_cg_scale, dim3(grid_for(n)), dim3(256), 0, st, b, sw, 1.0, n);
+    // Jacobi: diag(A) = diag(S), the exact self terms (the negated Dirichlet
+    // diagonal of the mixed operator)
+    BF_HIP(hipMemcpyAsync(ap, p->h_diag_dir.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_cg_diag, dim3(grid_for(n)), dim3(256), 0, st, ap, dinv, n, o.precond);
+    BF_HIP(hipGetLastError());
+    int status = 0, iters = 0;
+    double bn = 0.0, rel = 0.0;
+    {
+        int s2 = 0;
+        bn = norm2(b, n, ws, hp, st, &s2);
+        BF_CHECK(s2);
+    }
+    // r0 = b - A x0, z0 = dinv r0, p0 = z0 (slot 0)
+    if (o.use_x0) {
+        BF_HIP(hipMemcpyAsync(x, q, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_cg_scale, dim3(grid_for(n)), dim3(256), 0, st, x, sw, 1.0, n);
+        BF_CHECK(cg_op(p, x, sw, ws, ap, st));
+    } else {
+        BF_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+    }
+    hipLaunchKernelGGL(k_cg_init, dim3(kRedBlocks), dim3(256), 0, st, b, o.use_x0 ? ap : (const double *)nullptr,
+                       dinv, r, z, pv, n, ws.red);
+    hipLaunchKernelGGL(k_mdot_final, dim3(2), dim3(64), 0, st, ws.red, kRedBlocks, 2, sc, 0);
+    BF_HIP(hipGetLastError());
+    int cur = 0;
+    for (;;) {
+        BF_HIP(hipMemcpyAsync(hp, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        BF_HIP(hipStreamSynchronize(st));
+        const double rr = hp[4 * cur + 1];
+        if (iters > 0 && !(hp[4 * (cur ^ 1) + 2] > 0.0)) {
+            status = BEMFFT_EBREAKDOWN;
+            set_error("solve_cg: p.Ap <= 0 (the symmetrised operator is not positive definite)");
+            break;
+        }
+        if (!std::isfinite(rr)) {
+            status = BEMFFT_EBREAKDOWN;
+            set_error("solve_cg: non-finite residual");
+            break;
+        }
+        rel = bn > 0.0 ? std::sqrt(rr) / bn : 0.0;
+        if (rel <= o.tol || bn == 0.0) break;
+        if (iters >= o.maxit) {
+            status = BEMFFT_ENOCONV;
+            break;
+        }
+        // one iteration: Ap, p.Ap into slot cur, the step into slot cur^1, the new direction
+        BF_CHECK(cg_op(p, pv, sw, ws, ap, st));
+        BF_CHECK(mdot(pv, n, 1, ap, n, ws.red, sc + 4 * cur + 2, 0, st));
+        hipLaunchKernelGGL(k_cg_step, dim3(kRedBlocks), dim3(256), 0, st, sc, cur, x, r, z, pv, ap, dinv, n, ws.red);
+        hipLaunchKernelGGL(k_mdot_final, dim3(2), dim3(64), 0, st, ws.red, kRedBlocks, 2, sc + 4 * (cur ^ 1), 0);
+        hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(n)), dim3(256), 0, st, sc, cur, pv, z, n);
+        BF_HIP(hipGetLastError());
+        cur ^= 1;
+        ++iters;
+    }
+    // q = W^-1/2 x; true residual ||b - A x|| / ||b|| with a fresh apply
+    if (status >= 0) {
+        BF_CHECK(cg_op(p, x, sw, ws, ap, st));
+        hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, ap, b, 1.0, -1.0, n);
+        BF_HIP(hipGetLastError());
+        int s2 = 0;
+        const double tn = norm2(ap, n, ws, hp, st, &s2);
+        BF_CHECK(s2);
+        rel = bn > 0.0 ? tn / bn : 0.0;
+    }
+    hipLaunchKernelGGL(k_cg_in, dim3(grid_for(n)), dim3(256), 0, st, x, sw, q, ws.u, n);
+    BF_HIP(hipGetLastError());
+    BF_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->iters = iters;
+        info->restarts = 0;
+        info->true_relres = rel;
+        info->status = status;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->outer = 0;
+        info->applies64 = 0;
+        info->x0_used = o.use_x0;
+        info->x0_relres = -1.0;
     }
     return status;
 }
