@@ -41,11 +41,14 @@ def stage_bytes(info, prec_bytes):
     g = hx * nzo * py * cb                     # one complex field after the y transform
     spec = K * hx * hy * hz * prec_bytes       # octant spectra
     nodes_in = m * (8 * 2 * info["ncomp"] + 4 * 4 + 8 * 4)
+    ny = info["n"][1]
+    w = O * hx * ny * nzo * cb                 # inverse-y rows y < ny, kx contiguous
     return {
         "fwd_xy": F * g + nodes_in,
         "zpass": F * g + spec + O * g,
-        "inv_yx": O * g + m * 8 * O * 2,
-        "epilogue": m * 8 * O * (2 + 2 * O),
+        "inv_y": O * g + w,
+        # each row read once; per node: indices, c and self-term blocks, u, q, r
+        "gather": w + m * (4 * 4 + 8 * 2 * O * O + 8 * 3 * O),
     }
 
 
@@ -290,7 +293,7 @@ def bench_navier_star(B, I, dev, steps):
     n32, n64 = max(20, steps // 4), max(10, steps // 10)
     out["fp32_matvec_s"] = n32 / timed_applies(p32, q, u, r, n32, 5)
     out["fp64_matvec_s"] = n64 / timed_applies(p64, q, u, r, n64, 3)
-    names = ["fwd_xy", "zpass", "inv_yx", "epilogue"]
+    names = ["fwd_xy", "zpass", "inv_y", "gather"]
     out["fp32_stage_ms"] = dict(zip(names, B.bemfft_apply_profile(p32.handle, q, u, r, reps=20)))
     out["plan_seconds"] = {"fp32_keep_fp64": p32.info()["plan_seconds"], "fp64": p64.info()["plan_seconds"]}
     E = np.random.default_rng(11).normal(size=(3, 3))
@@ -482,7 +485,7 @@ def main():
     value = args.steps / dt
     stage_ms = B.bemfft_apply_profile(plan.handle, q, u, r, reps=max(20, args.steps // 4))
     sb = stage_bytes(info, 4)
-    names = ["fwd_xy", "zpass", "inv_yx", "epilogue"]
+    names = ["fwd_xy", "zpass", "inv_y", "gather"]
     stages = {n: {"ms": ms, "gbs": sb[n] / (ms * 1e-3) / 1e9, "bytes": sb[n]} for n, ms in zip(names, stage_ms)}
     dom = max(names, key=lambda n: stages[n]["ms"])
     apply_bytes = sum(sb.values())

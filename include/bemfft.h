@@ -133,7 +133,7 @@ int bemfft_apply(bemfft_plan *p, const double *q, const double *u, double *r, vo
 /*
  * Same as bemfft_apply, repeated 'reps' times with HIP events recorded on
  * 'stream' between the four stages (scatter + x/y transforms, z transform +
- * spectral products, inverse y transform + gather, epilogue); stage_ms[4]
+ * spectral products, inverse y transform, gather at the nodes); stage_ms[4]
  * receives the mean duration of each stage in milliseconds.  Synchronises
  * the stream.  For measurement only.  Errors: EINVAL, EDEVICE.
  */

@@ -207,7 +207,7 @@ def bemfft_eval_grid(plan, q, u, out, stream=None):
 
 
 def bemfft_apply_profile(plan, q, u, r, reps=10, stream=None):
-    """Mean per-stage milliseconds (fwd_xy, zpass, inv_yx, epilogue)."""
+    """Mean per-stage milliseconds (fwd_xy, zpass, inv_y, gather)."""
     ms = (ctypes.c_double * 4)()
     _check(load().bemfft_apply_profile(plan, _ptr(q), _ptr(u), _ptr(r), int(reps), ms, _stream_ptr(stream)),
            "bemfft_apply_profile")

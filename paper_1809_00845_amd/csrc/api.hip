@@ -96,7 +96,6 @@ void free_engine(Engine *e) {
     dev_free(e->twz);
     dev_free(e->Y);
     dev_free(e->Z);
-    dev_free(e->partial);
     dev_free(e->vf);
     dev_free(e->Xd);
     *e = Engine{};
@@ -116,12 +115,6 @@ static int upload_tw(Engine *e, const bemfft_plan *p) {
 
 int upload_twiddles(Engine *e, const bemfft_plan *p) {
     return e->precision == BEMFFT_FP32 ? upload_tw<float>(e, p) : upload_tw<double>(e, p);
-}
-
-static int inv_kxc(int kernel, int precision, int py) {
-    if (kernel == 0) return inv_kxc_kind<0>(precision, py);
-    if (kernel == 1) return inv_kxc_kind<1>(precision, py);
-    return inv_kxc_kind<2>(precision, py);
 }
 
 int alloc_workspace(bemfft_plan *p, Engine *e) {
@@ -149,9 +142,9 @@ void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, Ap
     a.z0 = (int)p->z0;
     a.nzo = (int)p->nzo;
     a.m = (int)p->m;
-    a.G = ws.G;
     a.gx = p->d_gx;
     a.gy = p->d_gy;
+    a.gz = p->d_gz;
     a.rowptr = p->d_rowptr;
     a.perm = p->d_perm;
     a.w = p->d_w;
@@ -164,13 +157,11 @@ void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, Ap
     a.twz = e.twz;
     a.Y = ws.Y;
     a.Z = ws.Z;
-    a.partial = ws.partial;
     a.vf = ws.vf;
     a.Xd = ws.Xd;
     a.row_dense = p->d_row_dense;
     a.dense_rows = p->d_dense_rows;
     a.nd = (int)p->nd;
-    a.node_splits = (int)std::max<int64_t>(1, (p->max_plane_nodes + kGatherChunk - 1) / kGatherChunk);
     a.zsched = p->zsched;
     a.off = 0;
     a.gid = 0;
@@ -182,23 +173,15 @@ int alloc_intermediates(const bemfft_plan *p, int precision, Engine *e) {
     e->creal = precision == BEMFFT_FP32 ? 4 : 8;
     const size_t cb = 2 * e->creal;
     const size_t rows = (size_t)p->H[0] * p->nzo * p->P[1];
-    const int kxc = inv_kxc(p->kernel, e->precision, (int)p->P[1]);
-    if (kxc <= 0) {
-        set_error("unsupported y length");
-        return BEMFFT_EUNSUPPORTED;
-    }
-    e->G = (int)((p->H[0] + kxc - 1) / kxc);
     const size_t ysz = (size_t)p->F * rows * cb, zsz = (size_t)p->O * rows * cb;
-    const size_t psz = (size_t)e->G * p->O * p->m * sizeof(double);
     const size_t vsz = (size_t)p->F * p->m * e->creal;
     const size_t xsz = std::max<size_t>(1, (size_t)p->nd * p->F * p->H[0] * cb);
     if (hipMalloc(&e->Y, ysz) != hipSuccess || hipMalloc(&e->Z, zsz) != hipSuccess ||
-        hipMalloc(&e->partial, psz) != hipSuccess || hipMalloc(&e->vf, vsz) != hipSuccess ||
-        hipMalloc(&e->Xd, xsz) != hipSuccess) {
+        hipMalloc(&e->vf, vsz) != hipSuccess || hipMalloc(&e->Xd, xsz) != hipSuccess) {
         set_error("hipMalloc of the intermediates failed");
         return BEMFFT_ENOMEM;
     }
-    e->bytes = ysz + zsz + psz + vsz + xsz;
+    e->bytes = ysz + zsz + vsz + xsz;
     return 0;
 }
 
@@ -379,7 +362,6 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     // long rows get their x-transform from a row FFT
     std::vector<int> row_dense((size_t)p->nzo * ny, -1), dense_rows;
     for (int64_t z = 0; z < p->nzo; ++z) {
-        p->max_plane_nodes = std::max<int64_t>(p->max_plane_nodes, rowptr[(z + 1) * ny] - rowptr[z * ny]);
         for (int64_t y = 0; y < ny; ++y) {
             const int64_t row = z * ny + y;
             if (rowptr[row + 1] - rowptr[row] >= kDenseRow) {

@@ -9,11 +9,13 @@
 //              outside the occupied planes), products with the compact kernel
 //              spectra summed into each output (eqs. 15-16), inverse z-FFT,
 //              keep the occupied planes.              -> Z[o][kx][z][ky]
-//   k_inv_yx   per occupied z-plane and chunk of kx: inverse y-FFT in LDS, then
-//              the inverse x-transform evaluated only at the plane's nodes
-//              ("the values of interest lie only on the boundary", Sec. 4);
-//              one partial sum per chunk.              -> partial[g][o][node]
-//   k_epilogue per node: sum of the chunks + c u + self-term correction.
+//   k_inv_y    per occupied z-plane and chunk of kx: inverse y-FFT in
+//              registers/LDS, rows y < ny stored with kx contiguous
+//                                                      -> W[o][z][y][kx] (in Y)
+//   k_gather   eight lanes per node: the inverse x-transform of its row
+//              evaluated only at its own x ("the values of interest lie only
+//              on the boundary", Sec. 4), plus c u and the self-term
+//              correction                              -> r
 //
 // Layout: complex intermediates are interleaved (re, im) in the working
 // precision R with ky contiguous, so every global access is a run of whole
@@ -36,12 +38,10 @@ struct ApplyArgs {
     int hx, hy, hz;
     int z0, nzo;
     int m;
-    int G;
-    int node_splits;  // node chunks per plane in the gather
     int zsched;       // radix schedule of the z pass (0 or 1)
     int64_t off;      // batched apply: offset of this member's q, u, r
     int gid;          // batched apply: member index in the whole batch
-    const int *gx, *gy, *rowptr, *perm;
+    const int *gx, *gy, *gz, *rowptr, *perm;
     const double *w, *nrm, *C, *SC;
     const double *q, *u;
     double *r;
@@ -52,15 +52,14 @@ struct ApplyArgs {
     const int *dense_rows;  // [nd]: row index (zz * ny + y) of each long row
     int nd;
     void *Y, *Z;
-    double *partial;
 };
 
 // Launch extents of one group of batch members (same family, precision,
 // padded sizes and schedule): the largest per-member extents.
 struct GroupDims {
     int nmem;
-    int max_m, max_nd, max_nzo, max_splits;
-    int G, hx, px, py, pz, zsched;
+    int max_m, max_nd, max_nzo;
+    int hx, px, py, pz, zsched;
 };
 
 // Base pointers of a batched apply (device memory, so that a captured graph
@@ -74,7 +73,6 @@ struct BatchIO {
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int mini(int a, int b) { return a < b ? a : b; }
 constexpr int kMaxPx = 512;          // largest padded length along x
-constexpr int kGatherChunk = 2048;   // nodes per gather block
 
 // (k x) mod p for 0 <= k x < 2^24, with a float estimate of the quotient.
 __device__ __forceinline__ int mod_small(int kx, int x, int p, float inv_p) {
@@ -526,106 +524,140 @@ __global__ __launch_bounds__(256) void kb_mac2d(const ApplyArgs *members, const 
     mac2d_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
 }
 
-// ------------------------------------------------------------------ k_inv_yx
+// ------------------------------------------------------------------ k_inv_y
 template <typename R, int PY, int KIND>
-struct InvCfg {
+struct InvYCfg {
     static constexpr int O = Terms<KIND>::O;
     static constexpr int TPP = PencilShape<PY>::TPP;
     static constexpr int CB = (int)sizeof(cx<R>);
     static constexpr int PS = pstride<PY>();
-    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - (PY + kMaxPx) * CB) / (O * PS * CB)), 1, 16);
+    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - PY * CB) / (O * PS * CB)), 1, 16);
     static constexpr int NT = O * KXC * TPP;
 };
 
 template <typename R, int PY, int KIND>
-__device__ __forceinline__ void inv_yx_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
+__device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, const int by) {
     if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
-    using Cfg = InvCfg<R, PY, KIND>;
+    using Cfg = InvYCfg<R, PY, KIND>;
     constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
     __shared__ cx<R> buf[O * KXC * PS];
     __shared__ cx<R> tw[PY];
-    __shared__ cx<R> twx[kMaxPx];
     const int tid = threadIdx.x;
-    const int g = bx;
-    const int kx0 = g * KXC;
+    const int kx0 = bx * KXC;
     const int zz = by;
-    // this block's share of the plane's nodes; empty shares leave at once
-    const int p0 = a.rowptr[zz * a.ny], p1 = a.rowptr[(zz + 1) * a.ny];
-    const int s0 = p0 + bz * kGatherChunk;
-    const int s1 = min(p1, s0 + kGatherChunk);
-    if (s0 >= s1) return;
-    const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
     const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
     for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
-    for (int i = tid; i < a.px; i += NT) twx[i] = gtwx[i];
-    // each pencil row (one output, one kx) is loaded straight into registers
     const int pen = tid / TPP, t = tid % TPP;
     const int o = pen / KXC, kx = kx0 + pen % KXC;
     cx<R> x[E];
-    const cx<R> *Zr = static_cast<const cx<R> *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
+    if (kx < a.hx) {
+        const cx<R> *Zr = static_cast<const cx<R> *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
 #pragma unroll
-    for (int e = 0; e < E; ++e) x[e] = kx < a.hx ? Zr[t + e * TPP] : cx<R>{R(0), R(0)};
-    __syncthreads();  // twiddle tables
+        for (int e = 0; e < E; ++e) x[e] = Zr[t + e * TPP];
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = {R(0), R(0)};
+    }
+    __syncthreads();  // twiddle table
     cx<R> *pb = buf + pen * PS;
     fft_regs<R, PY, 1>(x, pb, tw, t);
     wave_lds_sync();
 #pragma unroll
-    for (int e = 0; e < E / 2; ++e) {  // rows y >= P/2 are never gathered
+    for (int e = 0; e < E / 2; ++e) {  // ny <= Py/2: rows y >= Py/2 hold no node
         const int y = t + e * TPP;
         if (y < a.ny) pb[pslot(y)] = x[e];
     }
-    __syncthreads();  // the gather reads every pencil
-    const float inv_px = 1.0f / (float)a.px;
+    __syncthreads();  // the transposed store reads every pencil
     const int nk = min(KXC, a.hx - kx0);
-    for (int s = s0 + tid; s < s1; s += NT) {
-        const int y = a.gy[s], xg = a.gx[s];
-        double accd[O];
-#pragma unroll
-        for (int oo = 0; oo < O; ++oo) accd[oo] = 0.0;
-        int idx = mod_small(kx0, xg, a.px, inv_px);  // (kx x) mod px, stepped below
-        for (int kxl = 0; kxl < nk; ++kxl) {
-            const int kxx = kx0 + kxl;
-            const cx<R> w = twx[idx];
-            const double cf = (kxx == 0 || 2 * kxx == a.px) ? 1.0 : 2.0;
-#pragma unroll
-            for (int oo = 0; oo < O; ++oo) {
-                const cx<R> v = buf[(oo * KXC + kxl) * PS + pslot(y)];
-                accd[oo] += cf * (double)(v.x * w.x + v.y * w.y);  // Re(v conj(w))
-            }
-            idx += xg;
-            if (idx >= a.px) idx -= a.px;
-        }
-#pragma unroll
-        for (int oo = 0; oo < O; ++oo) a.partial[((size_t)g * O + oo) * a.m + s] = accd[oo];
+    cx<R> *W = static_cast<cx<R> *>(a.Y);
+    for (int i = tid; i < O * a.ny * KXC; i += NT) {
+        const int kl = i % KXC, rest = i / KXC;
+        const int y = rest % a.ny, oo = rest / a.ny;
+        if (kl < nk) W[((size_t)(oo * a.nzo + zz) * a.ny + y) * a.hx + kx0 + kl] = buf[(oo * KXC + kl) * PS + pslot(y)];
     }
 }
 
 template <typename R, int PY, int KIND>
-__global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void k_inv_yx(ApplyArgs a) {
-    inv_yx_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void k_inv_y(ApplyArgs a) {
+    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
 template <typename R, int PY, int KIND>
-__global__ __launch_bounds__((InvCfg<R, PY, KIND>::NT)) void kb_inv_yx(const ApplyArgs *members, const BatchIO *io, int zdiv) {
-    ApplyArgs a = members[blockIdx.z / zdiv];
+__global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void kb_inv_y(const ApplyArgs *members, const BatchIO *io, int zdiv) {
+    const ApplyArgs &a = members[blockIdx.z / zdiv];
     if (io->active && !io->active[a.gid]) return;
-    a.q = io->q + a.off;
-    a.u = io->u + a.off;
-    a.r = io->r + a.off;
-    inv_yx_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y);
 }
 
-// ------------------------------------------------------------------ epilogue
-template <int O>
-__device__ __forceinline__ void epilogue_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
-    const int s = bx * 256 + threadIdx.x;
-    if (s >= a.m) return;
+// ------------------------------------------------------------------ k_gather
+// Eight lanes per node: the inverse x transform of the node's row in W,
+//   sum_kx cf Re(W[kx] exp(+2 pi i kx x / Px)),  cf = 1 at kx = 0 and Px/2,
+//   2 between (the real field from its half spectrum),
+// evaluated at the node's x only.  Lane l of a node takes kx = 1 + l, 9 + l,
+// ... (the eight lanes read consecutive coefficients), accumulates in FP64,
+// and a fixed shuffle tree sums the lanes (reproducible); the first lane
+// adds kx = 0, Px/2 and r = c u - (exact - grid) self term q.
+constexpr int kGatherLanes = 8;
+
+template <typename R, int KIND>
+__device__ __forceinline__ void gather_body(const ApplyArgs &a, const int bx) {
+    constexpr int O = Terms<KIND>::O, L = kGatherLanes;
+    __shared__ cx<R> twx[kMaxPx];
+    const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
+    for (int i = threadIdx.x; i < a.px; i += 256) twx[i] = gtwx[i];
+    __syncthreads();
+    const int sub = threadIdx.x % L;
+    const int s = bx * (256 / L) + threadIdx.x / L;
+    if (s >= a.m) return;  // the node's eight lanes leave together
+    const int zz = a.gz[s] - a.z0, y = a.gy[s], xg = a.gx[s];
+    const int hx = a.hx, px = a.px;
+    const size_t rstride = (size_t)a.nzo * a.ny * hx;  // between outputs
+    const cx<R> *row = static_cast<const cx<R> *>(a.Y) + ((size_t)zz * a.ny + y) * hx;
+    double acc[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) acc[o] = 0.0;
+    const int step = (L * xg) % px;
+    int idx = ((1 + sub) * xg) % px;  // (kx x) mod px
+    int kx = 1 + sub;
+    // four coefficients per output in flight before they are used
+    for (; kx + 3 * L < hx - 1; kx += 4 * L) {
+        cx<R> v[4][O];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int o = 0; o < O; ++o) v[k][o] = row[o * rstride + kx + k * L];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const cx<R> w = twx[idx];
+#pragma unroll
+            for (int o = 0; o < O; ++o) acc[o] += (double)(v[k][o].x * w.x + v[k][o].y * w.y);
+            idx += step;
+            if (idx >= px) idx -= px;
+        }
+    }
+    for (; kx < hx - 1; kx += L) {
+        const cx<R> w = twx[idx];
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const cx<R> v = row[o * rstride + kx];
+            acc[o] += (double)(v.x * w.x + v.y * w.y);
+        }
+        idx += step;
+        if (idx >= px) idx -= px;
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int o = 0; o < O; ++o) acc[o] += __shfl_xor(acc[o], off, 64);
+    if (sub != 0) return;
+    const R wn = (xg & 1) ? R(-1) : R(1);  // exp(i pi x)
     const int j = a.perm[s];
 #pragma unroll
     for (int o = 0; o < O; ++o) {
-        double v = 0.0;
-        for (int g = 0; g < a.G; ++g) v += a.partial[((size_t)g * O + o) * a.m + s];
+        const cx<R> v0 = row[o * rstride];
+        const cx<R> vn = row[o * rstride + hx - 1];
+        double v = (double)v0.x + (double)(vn.x * wn) + 2.0 * acc[o];
 #pragma unroll
         for (int l = 0; l < O; ++l) {
             v += a.C[((size_t)s * O + o) * O + l] * a.u[l * a.m + j];
@@ -635,20 +667,20 @@ __device__ __forceinline__ void epilogue_body(const ApplyArgs &a, const int bx, 
     }
 }
 
-template <int O>
-__global__ __launch_bounds__(256) void k_epilogue(ApplyArgs a) {
-    epilogue_body<O>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_gather(ApplyArgs a) {
+    gather_body<R, KIND>(a, blockIdx.x);
 }
 
-// Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
-template <int O>
-__global__ __launch_bounds__(256) void kb_epilogue(const ApplyArgs *members, const BatchIO *io, int zdiv) {
-    ApplyArgs a = members[blockIdx.z / zdiv];
+// Batched form: blockIdx.z = member.
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void kb_gather(const ApplyArgs *members, const BatchIO *io) {
+    ApplyArgs a = members[blockIdx.z];
     if (io->active && !io->active[a.gid]) return;
     a.q = io->q + a.off;
     a.u = io->u + a.off;
     a.r = io->r + a.off;
-    epilogue_body<O>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+    gather_body<R, KIND>(a, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -661,10 +693,10 @@ int launch_fwd(const ApplyArgs &a, hipStream_t st) {
     return 0;
 }
 template <typename R, int PY, int KIND>
-int launch_inv(const ApplyArgs &a, hipStream_t st) {
-    using Cfg = InvCfg<R, PY, KIND>;
-    dim3 grid(a.G, a.nzo, a.node_splits);
-    hipLaunchKernelGGL((k_inv_yx<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+int launch_inv_y(const ApplyArgs &a, hipStream_t st) {
+    using Cfg = InvYCfg<R, PY, KIND>;
+    dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
+    hipLaunchKernelGGL((k_inv_y<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a);
     BF_HIP(hipGetLastError());
     return 0;
 }
@@ -709,11 +741,10 @@ struct Launch {
         BF_HIP(hipGetLastError());
         return 0;
     }
-    template <int P> static int inv(const ApplyArgs &a, hipStream_t st) { return launch_inv<R, P, KIND>(a, st); }
+    template <int P> static int inv_y(const ApplyArgs &a, hipStream_t st) { return launch_inv_y<R, P, KIND>(a, st); }
     template <int P> static int z(const ApplyArgs &a, hipStream_t st) {
         return a.zsched ? launch_z<R, P, KIND, 1>(a, st) : launch_z<R, P, KIND, 0>(a, st);
     }
-    template <int P> static int kxc(int) { return InvCfg<R, P, KIND>::KXC; }
 
     // Fields, forward x/y and the z pass: everything up to Z.  ev (optional):
     // events 0-2 recorded around the two stages.
@@ -734,9 +765,10 @@ struct Launch {
     // ev (optional): five events recorded around the four stages.
     static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
         BF_CHECK(front(a, st, ev));
-        BF_CHECK(dispatch_inv(a, st));
+        BF_CHECK(dispatch_inv_y(a, st));
         if (ev) BF_HIP(hipEventRecord(ev[3], st));
-        hipLaunchKernelGGL((k_epilogue<Terms<KIND>::O>), dim3((a.m + 255) / 256), dim3(256), 0, st, a);
+        constexpr int NPB = 256 / kGatherLanes;  // nodes per block
+        hipLaunchKernelGGL((k_gather<R, KIND>), dim3((a.m + NPB - 1) / NPB), dim3(256), 0, st, a);
         BF_HIP(hipGetLastError());
         if (ev) BF_HIP(hipEventRecord(ev[4], st));
         return 0;
@@ -762,9 +794,9 @@ struct Launch {
         return 0;
     }
     template <int P> static int binv(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
-        using Cfg = InvCfg<R, P, KIND>;
-        dim3 grid(g.G, g.max_nzo, g.nmem * g.max_splits);
-        hipLaunchKernelGGL((kb_inv_yx<R, P, KIND>), grid, dim3(Cfg::NT), 0, st, dm, io, g.max_splits);
+        using Cfg = InvYCfg<R, P, KIND>;
+        dim3 grid((g.hx + Cfg::KXC - 1) / Cfg::KXC, g.max_nzo, g.nmem);
+        hipLaunchKernelGGL((kb_inv_y<R, P, KIND>), grid, dim3(Cfg::NT), 0, st, dm, io, 1);
         BF_HIP(hipGetLastError());
         return 0;
     }
@@ -850,8 +882,8 @@ struct Launch {
             default: break;
         }
         BF_CHECK(s5);
-        hipLaunchKernelGGL((kb_epilogue<Terms<KIND>::O>), dim3((g.max_m + 255) / 256, 1, g.nmem), dim3(256), 0, st, dm,
-                           io, 1);
+        constexpr int NPB = 256 / kGatherLanes;  // nodes per block
+        hipLaunchKernelGGL((kb_gather<R, KIND>), dim3((g.max_m + NPB - 1) / NPB, 1, g.nmem), dim3(256), 0, st, dm, io);
         BF_HIP(hipGetLastError());
         return 0;
     }
@@ -861,8 +893,8 @@ struct Launch {
         set_error("unsupported x length");
         return BEMFFT_EUNSUPPORTED;
     }
-    static int dispatch_inv(const ApplyArgs &a, hipStream_t st) {
-        BF_SIZE_SWITCH(a.py, inv, a, st);
+    static int dispatch_inv_y(const ApplyArgs &a, hipStream_t st) {
+        BF_SIZE_SWITCH(a.py, inv_y, a, st);
         set_error("unsupported y length");
         return BEMFFT_EUNSUPPORTED;
     }
@@ -877,25 +909,19 @@ struct Launch {
             return BEMFFT_EUNSUPPORTED;
         }
     }
-    static int inv_kxc(int py) {
-        BF_SIZE_SWITCH(py, kxc, 0);
-        return 0;
-    }
 };
 
 // Per-family entry points, instantiated in one source file per family.
 template <int KIND>
 int apply_kind(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t *ev);
 template <int KIND>
-int inv_kxc_kind(int precision, int py);
-template <int KIND>
 int apply_batch_kind(int precision, const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st);
 
 // Apply arguments of plan p with the spectra/tables of 'shared' and the
 // intermediate buffers of 'ws' (q, u, r left null).
 void fill_apply_args(const bemfft_plan *p, const Engine &shared, const Engine &ws, ApplyArgs *a);
-// Intermediate buffers of one apply of plan p (Y, Z, partial, fields, long
-// rows), without spectra or tables.
+// Intermediate buffers of one apply of plan p (Y, Z, fields, long rows),
+// without spectra or tables.
 int alloc_intermediates(const bemfft_plan *p, int precision, Engine *e);
 
 }  // namespace bemfft

@@ -10,12 +10,6 @@ int apply_kind<2>(int precision, const ApplyArgs &a, hipStream_t st, hipEvent_t 
 }
 
 template <>
-int inv_kxc_kind<2>(int precision, int py) {
-    if (precision == BEMFFT_FP32) return Launch<float, 2>::inv_kxc(py);
-    return Launch<double, 2>::inv_kxc(py);
-}
-
-template <>
 int apply_batch_kind<2>(int precision, const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
     if (precision == BEMFFT_FP32) return Launch<float, 2>::run_batch(dm, io, g, st);
     return Launch<double, 2>::run_batch(dm, io, g, st);

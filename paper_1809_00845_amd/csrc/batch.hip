@@ -347,8 +347,7 @@ int bemfft_batch_create(bemfft_batch **out, bemfft_plan *const *plans, int nplan
             Group g;
             g.kernel = b->kernel;
             g.precision = b->precision;
-            g.dims = GroupDims{0, 0, 0, 0, 1, b->ws[k].G, (int)p->H[0], (int)p->P[0], (int)p->P[1], (int)p->P[2],
-                               p->zsched};
+            g.dims = GroupDims{0, 0, 0, 0, (int)p->H[0], (int)p->P[0], (int)p->P[1], (int)p->P[2], p->zsched};
             gidx[key] = (int)b->groups.size();
             b->groups.push_back(g);
             it = gidx.find(key);
@@ -359,8 +358,6 @@ int bemfft_batch_create(bemfft_batch **out, bemfft_plan *const *plans, int nplan
         g.dims.max_m = std::max<int>(g.dims.max_m, (int)p->m);
         g.dims.max_nd = std::max<int>(g.dims.max_nd, (int)p->nd);
         g.dims.max_nzo = std::max<int>(g.dims.max_nzo, (int)p->nzo);
-        g.dims.max_splits = std::max<int>(
-            g.dims.max_splits, (int)std::max<int64_t>(1, (p->max_plane_nodes + kGatherChunk - 1) / kGatherChunk));
     }
     for (auto &g : b->groups) {
         if (status) break;

@@ -56,10 +56,8 @@ struct Engine {
     void *twz = nullptr;          // [Pz]
     void *Y = nullptr;            // [F][Hx][nzo][Py] complex
     void *Z = nullptr;            // [O][Hx][nzo][Py] complex
-    double *partial = nullptr;    // [G][O][m]
     void *vf = nullptr;           // [F][m] sorted boundary fields
     void *Xd = nullptr;           // [nd][F][Hx] transforms of the long rows
-    int G = 0;                    // kx chunks of the inverse pass
     size_t bytes = 0;
 };
 
@@ -73,7 +71,6 @@ struct bemfft_plan {
     int64_t P[3] = {1, 1, 1};
     int64_t H[3] = {1, 1, 1};
     int64_t z0 = 0, nzo = 1;
-    int64_t max_plane_nodes = 0;  // largest node count of one grid plane
     int *d_row_dense = nullptr;   // [nzo * ny] long-row index or -1
     int *d_dense_rows = nullptr;  // [nd]
     int64_t nd = 0;               // rows whose x-transform is an FFT

@@ -3,12 +3,11 @@
 // points inside the boundary and c = 0 outside, Sec. 2) reads
 //     v(p) = S[q](p) - D[u](p),
 // and the inverse transform of the convolution gives it at every grid
-// point (Sec. 4), so the forward passes and the z pass of the apply are
-// reused unchanged and only the last stage differs:
+// point (Sec. 4), so the forward passes, the z pass and the inverse y pass
+// of the apply are reused unchanged and only the last stage differs:
 //
-//   k_vol_y  per occupied z-plane and chunk of kx: inverse y-FFT of every
-//            output, rows y < ny written with kx contiguous
-//                                                -> W[o][z][y][kx]  (in Y)
+//   k_inv_y  (the apply's own) inverse y-FFT of every output, rows y < ny
+//            written with kx contiguous            -> W[o][z][y][kx]  (in Y)
 //   k_vol_x  two grid rows per pencil: the half spectra of rows a and b are
 //            extended to Hermitian sequences A, B (imaginary parts at kx = 0
 //            and kx = Px/2 dropped, as the node gather does) and packed as
@@ -24,58 +23,6 @@
 #include "apply_impl.hpp"
 
 namespace bemfft {
-
-// ------------------------------------------------------------------ k_vol_y
-template <typename R, int PY, int KIND>
-struct VolYCfg {
-    static constexpr int O = Terms<KIND>::O;
-    static constexpr int TPP = PencilShape<PY>::TPP;
-    static constexpr int CB = (int)sizeof(cx<R>);
-    static constexpr int PS = pstride<PY>();
-    static constexpr int KXC = clampi(mini(256 / (O * TPP), (64 * 1024 - PY * CB) / (O * PS * CB)), 1, 16);
-    static constexpr int NT = O * KXC * TPP;
-};
-
-template <typename R, int PY, int KIND>
-__global__ __launch_bounds__((VolYCfg<R, PY, KIND>::NT)) void k_vol_y(ApplyArgs a) {
-    using Cfg = VolYCfg<R, PY, KIND>;
-    constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
-    __shared__ cx<R> buf[O * KXC * PS];
-    __shared__ cx<R> tw[PY];
-    const int tid = threadIdx.x;
-    const int kx0 = blockIdx.x * KXC;
-    const int zz = blockIdx.y;
-    const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
-    for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
-    const int pen = tid / TPP, t = tid % TPP;
-    const int o = pen / KXC, kx = kx0 + pen % KXC;
-    cx<R> x[E];
-    if (kx < a.hx) {
-        const cx<R> *Zr = static_cast<const cx<R> *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
-#pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = Zr[t + e * TPP];
-    } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = {R(0), R(0)};
-    }
-    __syncthreads();  // twiddle table
-    cx<R> *pb = buf + pen * PS;
-    fft_regs<R, PY, 1>(x, pb, tw, t);
-    wave_lds_sync();
-#pragma unroll
-    for (int e = 0; e < E / 2; ++e) {  // ny <= Py/2: rows y >= Py/2 lie outside the box
-        const int y = t + e * TPP;
-        if (y < a.ny) pb[pslot(y)] = x[e];
-    }
-    __syncthreads();  // the transposed store reads every pencil
-    const int nk = min(KXC, a.hx - kx0);
-    cx<R> *W = static_cast<cx<R> *>(a.Y);
-    for (int i = tid; i < O * a.ny * KXC; i += NT) {
-        const int kl = i % KXC, rest = i / KXC;
-        const int y = rest % a.ny, oo = rest / a.ny;
-        if (kl < nk) W[((size_t)(oo * a.nzo + zz) * a.ny + y) * a.hx + kx0 + kl] = buf[(oo * KXC + kl) * PS + pslot(y)];
-    }
-}
 
 // ------------------------------------------------------------------ k_vol_x
 template <typename R, int PX>
@@ -135,13 +82,6 @@ __global__ __launch_bounds__((VolXCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__r
 // ------------------------------------------------------------------ launcher
 template <typename R, int KIND>
 struct VolumeLaunch {
-    template <int P> static int y(const ApplyArgs &a, hipStream_t st) {
-        using Cfg = VolYCfg<R, P, KIND>;
-        dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
-        hipLaunchKernelGGL((k_vol_y<R, P, KIND>), grid, dim3(Cfg::NT), 0, st, a);
-        BF_HIP(hipGetLastError());
-        return 0;
-    }
     template <int P> static int x(const ApplyArgs &a, double *out, hipStream_t st) {
         using Cfg = VolXCfg<R, P>;
         const int64_t nrows = (int64_t)Terms<KIND>::O * a.nzo * a.ny;
@@ -151,11 +91,6 @@ struct VolumeLaunch {
                            out);
         BF_HIP(hipGetLastError());
         return 0;
-    }
-    static int dispatch_y(const ApplyArgs &a, hipStream_t st) {
-        BF_SIZE_SWITCH(a.py, y, a, st);
-        set_error("unsupported y length");
-        return BEMFFT_EUNSUPPORTED;
     }
     static int dispatch_x(const ApplyArgs &a, double *out, hipStream_t st) {
         BF_SIZE_SWITCH(a.px, x, a, out, st);
@@ -168,7 +103,7 @@ struct VolumeLaunch {
         if (ev) BF_HIP(hipEventRecord(ev[0], st));
         BF_CHECK((Launch<R, KIND>::front(a, st, nullptr)));
         if (ev) BF_HIP(hipEventRecord(ev[1], st));
-        BF_CHECK(dispatch_y(a, st));
+        BF_CHECK((Launch<R, KIND>::dispatch_inv_y(a, st)));
         if (ev) BF_HIP(hipEventRecord(ev[2], st));
         BF_CHECK(dispatch_x(a, out, st));
         if (ev) BF_HIP(hipEventRecord(ev[3], st));
