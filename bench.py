@@ -82,13 +82,12 @@ def zpass_alu_view(info, ms):
     return {"flops": flops, "achieved_tflops": tf, "peak_tflops_unpacked_fp32": 78.65, "frac": tf / 78.65}
 
 
-def bench_grid_eval(plan, q, u, info, front_ms, steps):
+def bench_grid_eval(plan, q, u, info, steps):
     """S[q] - D[u] over the whole grid box (the representation formula
     inside the boundary), FP64 out.  The evaluation shares the apply's
-    forward passes and z pass; its own stages are the inverse y transform
-    to a kx-contiguous buffer and the inverse x transforms of two rows per
-    pencil.  Their algorithmic bytes: read O g, write O Hx ny nzo complex;
-    read that back, write O nx ny nzo doubles."""
+    forward passes, z pass and inverse y pass; its own last stage is the
+    inverse x transform of two grid rows per pencil (k_vol_x), whose
+    kernel time is in the rocprofv3 summary."""
     import torch
 
     out = None
@@ -100,15 +99,8 @@ def bench_grid_eval(plan, q, u, info, front_ms, steps):
         plan.eval_grid(q, u, out)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
-    px, py, _ = info["pad"]
-    nx, ny = info["n"][0], info["n"][1]
-    hx, nzo, O = px // 2 + 1, info["z_count"], info["noutputs"]
-    cb = 8  # FP32 complex
-    tail_bytes = O * hx * nzo * py * cb + 2 * O * hx * ny * nzo * cb + O * nx * ny * nzo * 8
-    tail_ms = ms - front_ms
-    return {"ms_per_eval": ms, "grid_points": nx * ny * nzo, "points_per_s": nx * ny * nzo * O / (ms * 1e-3),
-            "tail_ms": tail_ms, "tail_bytes": tail_bytes,
-            "tail_gbs": tail_bytes / (tail_ms * 1e-3) / 1e9 if tail_ms > 0 else None}
+    nx, ny, nzo, O = info["n"][0], info["n"][1], info["z_count"], info["noutputs"]
+    return {"ms_per_eval": ms, "grid_points": nx * ny * nzo, "points_per_s": nx * ny * nzo * O / (ms * 1e-3)}
 
 
 def bench_dirichlet_cg(B, I, dev):
@@ -477,9 +469,8 @@ def main():
     plan = B.Plan(cube, B.LAPLACE3D, precision=B.FP32, keep_fp64=True, autotune=1)
     info = plan.info()
     if args.grid_eval_only:
-        sm = B.bemfft_apply_profile(plan.handle, q, u, r, reps=20)
         print(json.dumps({"workload": "laplace3d cube 128^3 grid-box evaluation, fp32",
-                          **bench_grid_eval(plan, q, u, info, sm[0] + sm[1], args.steps)}), flush=True)
+                          **bench_grid_eval(plan, q, u, info, args.steps)}), flush=True)
         return
     dt = timed_applies(plan, q, u, r, args.steps, args.warmup)
     value = args.steps / dt
@@ -516,8 +507,7 @@ def main():
     if not args.quick:
         extra = {}
         # the field over the grid box (representation formula), same plan
-        extra["cube_grid_eval_fp32"] = bench_grid_eval(plan, q, u, info, stage_ms[0] + stage_ms[1],
-                                                       max(20, args.steps // 4))
+        extra["cube_grid_eval_fp32"] = bench_grid_eval(plan, q, u, info, max(20, args.steps // 4))
         # FP64 apply, same cube
         plan64 = B.Plan(cube, B.LAPLACE3D, precision=B.FP64, autotune=1)
         dt64 = timed_applies(plan64, q, u, r, max(20, args.steps // 4), 5)

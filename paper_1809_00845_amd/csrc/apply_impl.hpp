@@ -535,18 +535,23 @@ struct InvYCfg {
     static constexpr int NT = O * KXC * TPP;
 };
 
+// all_rows = 0 (the apply): only rows that hold nodes are stored, the
+// gather reads nothing else; all_rows = 1 (the grid evaluation): every row.
 template <typename R, int PY, int KIND>
-__device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, const int by) {
+__device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, const int by, const int all_rows) {
     if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
     using Cfg = InvYCfg<R, PY, KIND>;
     constexpr int O = Cfg::O, KXC = Cfg::KXC, NT = Cfg::NT, TPP = Cfg::TPP, PS = Cfg::PS, E = PY / TPP;
     __shared__ cx<R> buf[O * KXC * PS];
     __shared__ cx<R> tw[PY];
+    __shared__ unsigned char keep[PY / 2];
     const int tid = threadIdx.x;
     const int kx0 = bx * KXC;
     const int zz = by;
     const cx<R> *gtwy = static_cast<const cx<R> *>(a.twy);
     for (int i = tid; i < PY; i += NT) tw[i] = gtwy[i];
+    for (int y = tid; y < a.ny; y += NT)
+        keep[y] = all_rows || a.rowptr[zz * a.ny + y + 1] > a.rowptr[zz * a.ny + y];
     const int pen = tid / TPP, t = tid % TPP;
     const int o = pen / KXC, kx = kx0 + pen % KXC;
     cx<R> x[E];
@@ -558,7 +563,7 @@ __device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, con
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = {R(0), R(0)};
     }
-    __syncthreads();  // twiddle table
+    __syncthreads();  // twiddle table, row flags
     cx<R> *pb = buf + pen * PS;
     fft_regs<R, PY, 1>(x, pb, tw, t);
     wave_lds_sync();
@@ -573,13 +578,14 @@ __device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, con
     for (int i = tid; i < O * a.ny * KXC; i += NT) {
         const int kl = i % KXC, rest = i / KXC;
         const int y = rest % a.ny, oo = rest / a.ny;
-        if (kl < nk) W[((size_t)(oo * a.nzo + zz) * a.ny + y) * a.hx + kx0 + kl] = buf[(oo * KXC + kl) * PS + pslot(y)];
+        if (kl < nk && keep[y])
+            W[((size_t)(oo * a.nzo + zz) * a.ny + y) * a.hx + kx0 + kl] = buf[(oo * KXC + kl) * PS + pslot(y)];
     }
 }
 
 template <typename R, int PY, int KIND>
-__global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void k_inv_y(ApplyArgs a) {
-    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void k_inv_y(ApplyArgs a, int all_rows) {
+    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, all_rows);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -587,7 +593,7 @@ template <typename R, int PY, int KIND>
 __global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void kb_inv_y(const ApplyArgs *members, const BatchIO *io, int zdiv) {
     const ApplyArgs &a = members[blockIdx.z / zdiv];
     if (io->active && !io->active[a.gid]) return;
-    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y);
+    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, 0);
 }
 
 // ------------------------------------------------------------------ k_gather
@@ -693,10 +699,10 @@ int launch_fwd(const ApplyArgs &a, hipStream_t st) {
     return 0;
 }
 template <typename R, int PY, int KIND>
-int launch_inv_y(const ApplyArgs &a, hipStream_t st) {
+int launch_inv_y(const ApplyArgs &a, int all_rows, hipStream_t st) {
     using Cfg = InvYCfg<R, PY, KIND>;
     dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
-    hipLaunchKernelGGL((k_inv_y<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+    hipLaunchKernelGGL((k_inv_y<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a, all_rows);
     BF_HIP(hipGetLastError());
     return 0;
 }
@@ -741,7 +747,9 @@ struct Launch {
         BF_HIP(hipGetLastError());
         return 0;
     }
-    template <int P> static int inv_y(const ApplyArgs &a, hipStream_t st) { return launch_inv_y<R, P, KIND>(a, st); }
+    template <int P> static int inv_y(const ApplyArgs &a, int all_rows, hipStream_t st) {
+        return launch_inv_y<R, P, KIND>(a, all_rows, st);
+    }
     template <int P> static int z(const ApplyArgs &a, hipStream_t st) {
         return a.zsched ? launch_z<R, P, KIND, 1>(a, st) : launch_z<R, P, KIND, 0>(a, st);
     }
@@ -765,7 +773,7 @@ struct Launch {
     // ev (optional): five events recorded around the four stages.
     static int run(const ApplyArgs &a, hipStream_t st, hipEvent_t *ev = nullptr) {
         BF_CHECK(front(a, st, ev));
-        BF_CHECK(dispatch_inv_y(a, st));
+        BF_CHECK(dispatch_inv_y(a, 0, st));
         if (ev) BF_HIP(hipEventRecord(ev[3], st));
         constexpr int NPB = 256 / kGatherLanes;  // nodes per block
         hipLaunchKernelGGL((k_gather<R, KIND>), dim3((a.m + NPB - 1) / NPB), dim3(256), 0, st, a);
@@ -893,8 +901,10 @@ struct Launch {
         set_error("unsupported x length");
         return BEMFFT_EUNSUPPORTED;
     }
-    static int dispatch_inv_y(const ApplyArgs &a, hipStream_t st) {
-        BF_SIZE_SWITCH(a.py, inv_y, a, st);
+    // all_rows: store every row y < ny (the grid evaluation), not only those
+    // that hold nodes (the apply)
+    static int dispatch_inv_y(const ApplyArgs &a, int all_rows, hipStream_t st) {
+        BF_SIZE_SWITCH(a.py, inv_y, a, all_rows, st);
         set_error("unsupported y length");
         return BEMFFT_EUNSUPPORTED;
     }

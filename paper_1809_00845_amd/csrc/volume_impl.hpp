@@ -103,7 +103,7 @@ struct VolumeLaunch {
         if (ev) BF_HIP(hipEventRecord(ev[0], st));
         BF_CHECK((Launch<R, KIND>::front(a, st, nullptr)));
         if (ev) BF_HIP(hipEventRecord(ev[1], st));
-        BF_CHECK((Launch<R, KIND>::dispatch_inv_y(a, st)));
+        BF_CHECK((Launch<R, KIND>::dispatch_inv_y(a, 1, st)));
         if (ev) BF_HIP(hipEventRecord(ev[2], st));
         BF_CHECK(dispatch_x(a, out, st));
         if (ev) BF_HIP(hipEventRecord(ev[3], st));
