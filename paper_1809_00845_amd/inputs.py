@@ -177,17 +177,29 @@ def cube3d(n: int = 128, edge_points: int = 100) -> Geometry:
                     np.asarray([c, c, c]), f"cube{n}_{edge_points}")
 
 
-def _bin_surface(n, surf, ntheta, nphi, center, name, rows_per_chunk=64):
+def _bin_surface(n, surf, ntheta, nphi, center, name, rows_per_chunk=64, oversample=1, project=None):
     """Bin a parametric closed surface ``surf(theta, phi) -> (x, x_theta, x_phi)``
-    into half-open grid cells: weight = area, normal = mean outward normal."""
+    into half-open grid cells: weight = area, normal = mean outward normal.
+
+    oversample = s > 1: the pieces are the surface inside the half-open
+    cells of the coarser grid of spacing s h (n / s cells per axis), and each
+    node sits at its piece's area-weighted centroid, moved onto the surface
+    by ``project`` -- not on a grid point.  The geometry keeps the fine grid
+    (spacing h), so a plan snaps every node to within h/2 of its surface
+    point while the node count follows the coarse spacing."""
+    if n % oversample:
+        raise ValueError("the grid size must be a multiple of the oversampling factor")
     h = 1.0 / n
+    nc = n // oversample
+    hc = oversample * h
     dth = math.pi / ntheta
     dph = 2.0 * math.pi / nphi
     th_all = (np.arange(ntheta) + 0.5) * dth
     ph = (np.arange(nphi) + 0.5) * dph
-    ncell = n * n * n
+    ncell = nc * nc * nc
     acc_w = np.zeros(ncell)
     acc_n = np.zeros((3, ncell))
+    acc_x = np.zeros((3, ncell)) if oversample > 1 else None
     for s in range(0, ntheta, rows_per_chunk):
         th = th_all[s:s + rows_per_chunk]
         T, Ph = np.meshgrid(th, ph, indexing="ij")
@@ -195,22 +207,33 @@ def _bin_surface(n, surf, ntheta, nphi, center, name, rows_per_chunk=64):
         cr = np.cross(xt, xp)  # outward for (theta, phi) ordering
         da = np.linalg.norm(cr, axis=-1) * dth * dph
         nrm = cr / np.linalg.norm(cr, axis=-1, keepdims=True)
-        g = np.floor(x / h + 0.5).astype(np.int64)
-        if g.min() < 0 or g.max() >= n:
+        g = np.floor(x / hc + 0.5).astype(np.int64)
+        if g.min() < 0 or g.max() >= nc:
             raise ValueError("surface leaves the grid")
-        lin = (g[..., 0] * n + g[..., 1]) * n + g[..., 2]
+        lin = (g[..., 0] * nc + g[..., 1]) * nc + g[..., 2]
         lin = lin.ravel()
         acc_w += np.bincount(lin, weights=da.ravel(), minlength=ncell)
         for k in range(3):
             acc_n[k] += np.bincount(lin, weights=(nrm[..., k] * da).ravel(), minlength=ncell)
+            if acc_x is not None:
+                acc_x[k] += np.bincount(lin, weights=(x[..., k] * da).ravel(), minlength=ncell)
     sel = np.nonzero(acc_w > 0.0)[0]
     w = acc_w[sel]
     nv = (acc_n[:, sel] / w[None, :]).T
-    gx, rem = np.divmod(sel, n * n)
-    gy, gz = np.divmod(rem, n)
-    nodes = np.stack([gx, gy, gz], axis=1) * h
+    meta = {}
+    if acc_x is None:
+        gx, rem = np.divmod(sel, n * n)
+        gy, gz = np.divmod(rem, n)
+        nodes = np.stack([gx, gy, gz], axis=1) * h
+    else:
+        nodes = (acc_x[:, sel] / w[None, :]).T
+        if project is not None:
+            nodes = project(nodes)
+        if nodes.min() < 0.0 or nodes.max() >= 1.0 - 0.5 * h:
+            raise ValueError("surface leaves the grid")
+        meta = {"oversample": oversample, "node_spacing": hc}
     return Geometry(3, (n, n, n), h, (0.0, 0.0, 0.0), nodes, nv, w,
-                    np.asarray(center, dtype=np.float64), name)
+                    np.asarray(center, dtype=np.float64), name, meta)
 
 
 def _default_quadrature(n):
@@ -218,8 +241,11 @@ def _default_quadrature(n):
     return nt, 2 * nt
 
 
-def sphere3d(n: int = 128, radius: float = 0.35, center=(0.5, 0.5, 0.5), ntheta=None, nphi=None) -> Geometry:
-    """Sphere of ``radius`` voxelised on an ``n^3`` unit grid."""
+def sphere3d(n: int = 128, radius: float = 0.35, center=(0.5, 0.5, 0.5), ntheta=None, nphi=None,
+             oversample: int = 1) -> Geometry:
+    """Sphere of ``radius`` voxelised on an ``n^3`` unit grid; with
+    ``oversample`` = s the nodes follow the grid of spacing s/n and sit on
+    the sphere (see _bin_surface)."""
     nt, npf = _default_quadrature(n)
     ntheta, nphi = ntheta or nt, nphi or npf
     c = np.asarray(center, dtype=np.float64)
@@ -231,7 +257,12 @@ def sphere3d(n: int = 128, radius: float = 0.35, center=(0.5, 0.5, 0.5), ntheta=
         ep = np.stack([-sp, cp, np.zeros_like(sp)], axis=-1)
         return c + radius * er, radius * et, radius * st[..., None] * ep
 
-    return _bin_surface(n, surf, ntheta, nphi, c, f"sphere{n}_R{radius}")
+    def project(p):
+        d = p - c[None, :]
+        return c[None, :] + radius * d / np.linalg.norm(d, axis=1, keepdims=True)
+
+    name = f"sphere{n}_R{radius}" + (f"_os{oversample}" if oversample > 1 else "")
+    return _bin_surface(n, surf, ntheta, nphi, c, name, oversample=oversample, project=project)
 
 
 def real_sph_harm(l: int, m: int, theta, phi):

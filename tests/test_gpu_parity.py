@@ -600,3 +600,12 @@ def test_dirichlet_star_single_vs_batch_iterations(dev):
     assert st == si["status"]
     assert abs(info[0]["iters"] - si["iters"]) <= 1, (info[0], si)
     batch.close()
+
+
+@pytest.mark.parametrize("precision", [B.FP64, B.FP32])
+def test_oversampled_sphere_nodes_off_grid(dev, precision):
+    # nodes on the sphere at the spacing of a 16^3 grid, snapped by the plan
+    # to a 64^3 grid (P = 128): positions off the grid points
+    g = I.sphere3d(64, 0.35, oversample=4)
+    err, _ = _parity(dev, g, B.LAPLACE3D, precision, seed=7)
+    assert err < TOL[precision]

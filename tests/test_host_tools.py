@@ -81,3 +81,22 @@ def test_learned_summary():
     assert s["guess_relres_median"] == pytest.approx(0.7)
     rows[1]["status1"] = 1
     assert not LS.summary(rows)["all_converged"]
+
+
+def test_oversampled_sphere_generator():
+    """oversample = s: nodes follow the coarse spacing s h, sit on the sphere,
+    and snap to the fine grid within half a cell per axis."""
+    import numpy as np
+
+    from paper_1809_00845_amd import inputs as I
+
+    base = I.sphere3d(16, 0.35)
+    g = I.sphere3d(64, 0.35, oversample=4)
+    assert g.m == base.m and g.n == (64, 64, 64) and g.meta["oversample"] == 4
+    assert abs(g.weights.sum() - base.weights.sum()) < 1e-9
+    r = np.linalg.norm(g.nodes - g.center, axis=1)
+    assert np.abs(r - 0.35).max() < 1e-12
+    snapped = np.rint(g.nodes / g.h) * g.h
+    assert np.abs(snapped - g.nodes).max() <= 0.5 * g.h + 1e-15
+    # the s = 1 generator puts nodes on grid points
+    assert np.abs(np.rint(base.nodes / base.h) * base.h - base.nodes).max() < 1e-15
