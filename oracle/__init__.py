@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bem_oracle.c")
 _LIB = os.path.join(_HERE, "libbem_oracle.so")
 
-LAPLACE2D, LAPLACE3D, NAVIER3D = 0, 1, 2
+LAPLACE2D, LAPLACE3D, NAVIER3D, HALFSPACE = 0, 1, 2, 3
 C_HALF, C_USER, C_IMPLICIT = 0, 1, 2
 
 _lib = None
@@ -68,6 +68,8 @@ def lib():
                                    ctypes.c_long, lp, dp, dp, dp, dp, dp]
         L.orc_volume.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_long, lp, dp, dp, dp, dp, ctypes.c_long, lp, dp, dp]
+        L.orc_halfspace.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_self_halfspace.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -120,6 +122,21 @@ def kelvin_t(xi, n, nu):
     return out.reshape(3, 3)
 
 
+def halfspace(d, nu, mu):
+    """Boussinesq-Cerruti tensor K[a][b] at the surface offset d = target -
+    source (eq. 9)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(9)
+    lib().orc_halfspace(_d(d), nu, mu, _d(out))
+    return out.reshape(3, 3)
+
+
+def self_halfspace(w, nu, mu):
+    out = np.zeros(9)
+    lib().orc_self_halfspace(float(w), nu, mu, _d(out))
+    return out.reshape(3, 3)
+
+
 def self_laplace2d(w):
     return float(lib().orc_self_laplace2d(float(w)))
 
@@ -160,11 +177,11 @@ class Problem:
 
     @property
     def dim(self):
-        return 2 if self.kernel == LAPLACE2D else 3
+        return 2 if self.kernel in (LAPLACE2D, HALFSPACE) else 3
 
     @property
     def ncomp(self):
-        return 3 if self.kernel == NAVIER3D else 1
+        return 3 if self.kernel in (NAVIER3D, HALFSPACE) else 1
 
     @property
     def m(self):
@@ -254,7 +271,9 @@ def assemble(p: Problem):
 def c_matrix(p: Problem, cmode, cuser=None, c_implicit=None):
     """The free-term operator as a dense (nc m)^2 matrix (component-major)."""
     nc, m = p.ncomp, p.m
-    if cmode == C_HALF:
+    if p.kernel == HALFSPACE:  # r = K[sigma] - u whatever the mode
+        blocks = np.tile(-np.eye(nc).reshape(1, nc * nc), (m, 1))
+    elif cmode == C_HALF:
         blocks = np.tile(0.5 * np.eye(nc).reshape(1, nc * nc), (m, 1))
     elif cmode == C_USER:
         blocks = np.reshape(cuser, (m, nc * nc))

@@ -52,7 +52,7 @@
 
 #define ORC_PI 3.14159265358979323846264338327950288
 
-enum { ORC_LAPLACE2D = 0, ORC_LAPLACE3D = 1, ORC_NAVIER3D = 2 };
+enum { ORC_LAPLACE2D = 0, ORC_LAPLACE3D = 1, ORC_NAVIER3D = 2, ORC_HALFSPACE = 3 };
 enum { ORC_C_HALF = 0, ORC_C_USER = 1, ORC_C_IMPLICIT = 2 };
 
 /* ------------------------------------------------------------------ kernels */
@@ -133,6 +133,41 @@ void orc_self_kelvin(double w, const double n[3], double nu, double mu, double o
         }
 }
 
+/* Elastic half-space, eq. (9): surface displacement component a at the
+ * surface offset d = (target - source) due to a unit surface point load in
+ * direction b, z pointing into the solid (Boussinesq's solution for the
+ * normal load, Cerruti's for the tangential ones; Johnson, Contact
+ * Mechanics, Sec. 2.2, written with E = 2 mu (1 + nu)).  out[3 a + b]. */
+void orc_halfspace(const double d[2], double nu, double mu, double out[9])
+{
+    double x = d[0], y = d[1];
+    double r2 = x * x + y * y, r = sqrt(r2);
+    double e = 1.0 / (2.0 * ORC_PI * mu);
+    double t = 0.5 * (1.0 - 2.0 * nu) / r2; /* normal-tangential coupling */
+    out[0] = e * ((1.0 - nu) / r + nu * x * x / (r2 * r));
+    out[1] = e * nu * x * y / (r2 * r);
+    out[2] = -e * t * x; /* u_x from a normal load: towards the load */
+    out[3] = out[1];
+    out[4] = e * ((1.0 - nu) / r + nu * y * y / (r2 * r));
+    out[5] = -e * t * y;
+    out[6] = e * t * x;  /* u_z from a tangential load (reciprocity) */
+    out[7] = e * t * y;
+    out[8] = e * (1.0 - nu) / r;
+}
+
+/* The half-space tensor integrated over a square of area w centred on the
+ * load (constant traction on the node's own cell): the square of side s
+ * gives int 1/r = 4 s ln(1 + sqrt 2), int x^2/r^3 = int y^2/r^3 = half of
+ * that, and the odd components vanish.  out[3 a + b]. */
+void orc_self_halfspace(double w, double nu, double mu, double out[9])
+{
+    double i1 = 4.0 * sqrt(w) * log(1.0 + sqrt(2.0));
+    double e = 1.0 / (2.0 * ORC_PI * mu);
+    for (int i = 0; i < 9; ++i) out[i] = 0.0;
+    out[0] = out[4] = e * i1 * (1.0 - 0.5 * nu);
+    out[8] = e * i1 * (1.0 - nu);
+}
+
 /* Single-layer kernel value at grid offset 0, per unit weight: the flat-panel
  * integral for the reference measure h^(d-1), divided by that measure.  For
  * Navier the panel orientation is averaged: <n n> = I/3. */
@@ -143,6 +178,10 @@ void orc_grid_k0(int kernel, double h, double nu, double mu, double out[9])
         out[0] = orc_self_laplace2d(h) / h;
     } else if (kernel == ORC_LAPLACE3D) {
         out[0] = orc_self_laplace3d(h * h) / (h * h);
+    } else if (kernel == ORC_HALFSPACE) {
+        /* r = K[sigma] - u: the "single layer" of the generic loop is -K */
+        orc_self_halfspace(h * h, nu, mu, out);
+        for (int i = 0; i < 9; ++i) out[i] = -out[i] / (h * h);
     } else {
         double s = h;
         double i1 = 4.0 * s * log(1.0 + sqrt(2.0));
@@ -175,11 +214,14 @@ long orc_snap(int dim, long m, const double *nodes, double h, const double *orig
 static void single_block(int kernel, double nu, double mu, double h, const double *xi,
                          int same_cell, int same_node, double wk, const double *nk, double G[9])
 {
-    int nc = (kernel == ORC_NAVIER3D) ? 3 : 1;
+    int nc = (kernel == ORC_NAVIER3D || kernel == ORC_HALFSPACE) ? 3 : 1;
     if (same_node) {
         if (kernel == ORC_LAPLACE2D) G[0] = orc_self_laplace2d(wk);
         else if (kernel == ORC_LAPLACE3D) G[0] = orc_self_laplace3d(wk);
-        else orc_self_kelvin(wk, nk, nu, mu, G);
+        else if (kernel == ORC_HALFSPACE) {
+            orc_self_halfspace(wk, nu, mu, G);
+            for (int i = 0; i < 9; ++i) G[i] = -G[i];
+        } else orc_self_kelvin(wk, nk, nu, mu, G);
         return;
     }
     if (same_cell) {
@@ -196,6 +238,11 @@ static void single_block(int kernel, double nu, double mu, double h, const doubl
         double o[4];
         orc_laplace3d(xi, o);
         G[0] = o[0] * wk;
+    } else if (kernel == ORC_HALFSPACE) {
+        /* u_j = sum_k K(p_j - p_k) w_k sigma_k; xi = p_k - p_j; "S" = -K */
+        double d[2] = {-xi[0], -xi[1]};
+        orc_halfspace(d, nu, mu, G);
+        for (int i = 0; i < 9; ++i) G[i] *= -wk;
     } else {
         orc_kelvin_u(xi, nu, mu, G);
         for (int i = 0; i < 9; ++i) G[i] *= wk;
@@ -207,8 +254,8 @@ static void single_block(int kernel, double nu, double mu, double h, const doubl
 static void double_block(int kernel, double nu, const double *xi, int same_cell, double wk,
                          const double *nk, double H[9])
 {
-    int nc = (kernel == ORC_NAVIER3D) ? 3 : 1;
-    if (same_cell) {
+    int nc = (kernel == ORC_NAVIER3D || kernel == ORC_HALFSPACE) ? 3 : 1;
+    if (same_cell || kernel == ORC_HALFSPACE) { /* the half-space has no double layer */
         for (int i = 0; i < nc * nc; ++i) H[i] = 0.0;
         return;
     }
@@ -226,8 +273,8 @@ static void double_block(int kernel, double nu, const double *xi, int same_cell,
     }
 }
 
-static int ncomp_of(int kernel) { return kernel == ORC_NAVIER3D ? 3 : 1; }
-static int dim_of(int kernel) { return kernel == ORC_LAPLACE2D ? 2 : 3; }
+static int ncomp_of(int kernel) { return (kernel == ORC_NAVIER3D || kernel == ORC_HALFSPACE) ? 3 : 1; }
+static int dim_of(int kernel) { return (kernel == ORC_LAPLACE2D || kernel == ORC_HALFSPACE) ? 2 : 3; }
 
 /* ---------------------------------------------------------------- the apply */
 
@@ -277,7 +324,9 @@ int orc_apply(int kernel, double nu, double mu, double h, long m, const long *gr
                 }
         }
         double C[9] = {0};
-        if (cmode == ORC_C_HALF) {
+        if (kernel == ORC_HALFSPACE) { /* r = K[sigma] - u */
+            for (int a = 0; a < nc; ++a) C[a * nc + a] = -1.0;
+        } else if (cmode == ORC_C_HALF) {
             for (int a = 0; a < nc; ++a) C[a * nc + a] = 0.5;
         } else if (cmode == ORC_C_USER) {
             for (int i = 0; i < nc * nc; ++i) C[i] = cuser[j * nc * nc + i];

@@ -406,6 +406,20 @@ def star3d(n: int, spec: StarSpec, center=(0.5, 0.5, 0.5), ntheta=None, nphi=Non
 # --------------------------------------------------------------------------- data
 
 
+def halfspace_patch(n: int = 256, radius: float | None = None, center=(0.5, 0.5)) -> Geometry:
+    """Surface nodes of an elastic half-space on an ``n^2`` unit grid: every
+    grid point (radius None) or those within ``radius`` of ``center`` (a
+    circular contact patch).  Weight = cell area h^2; normals are unused."""
+    h = 1.0 / n
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pts = np.stack([x.ravel(), y.ravel()], axis=1) * h
+    if radius is not None:
+        pts = pts[np.linalg.norm(pts - np.asarray(center)[None, :], axis=1) <= radius]
+    m = pts.shape[0]
+    return Geometry(2, (n, n, 1), h, (0.0, 0.0), pts, np.zeros((m, 2)), np.full(m, h * h),
+                    np.asarray(center, dtype=np.float64), f"halfspace{n}" + (f"_a{radius}" if radius else ""))
+
+
 def harmonic_2d_x2y2(geom: Geometry):
     """u = x^2 - y^2 (relative to the centre) at the nodes and its flux
     q = n . grad u with the node's mean normal."""
