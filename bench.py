@@ -134,6 +134,53 @@ def bench_dirichlet_cg(B, I, dev):
     return res
 
 
+def bench_halfspace(B, I, dev, steps):
+    """The elastic half-space of eq. (9) on the 256^2 surface (P = 512): the
+    convolution the paper starts from, run on the same engine.  Applies
+    with loads on every grid point (FP32, FP64), and the frictionless Hertz
+    contact on a disc of radius 0.3 (normal displacement given, shear
+    traction zero) solved to 1e-6."""
+    import torch
+
+    nu, mu = 0.3, 1.0
+    out = {}
+    g = I.halfspace_patch(256)
+    rng = np.random.default_rng(0)
+    q = torch.tensor(rng.uniform(-1, 1, (3, g.m)), device=dev)
+    u = torch.zeros_like(q)
+    r = torch.empty_like(q)
+    for tag, prec in (("fp32", B.FP32), ("fp64", B.FP64)):
+        pl = B.Plan(g, B.HALFSPACE, precision=prec, nu=nu, mu=mu)
+        out[f"full_surface_{tag}_matvec_s"] = steps / timed_applies(pl, q, u, r, steps, 5)
+        pl.close()
+    a, p0, E = 0.3, 1.0, 2 * mu * (1 + nu)
+    gd = I.halfspace_patch(256, a)
+    rr = np.sum((gd.nodes - gd.center) ** 2, axis=1)
+    bc = np.zeros((3, gd.m), dtype=np.uint8)
+    bc[:2] = 1
+    known = np.zeros((3, gd.m))
+    known[2] = np.pi * (1 - nu ** 2) * p0 * (2 * a ** 2 - rr) / (4 * a * E)
+    bct = torch.tensor(bc.reshape(-1), device=dev)
+    kt = torch.tensor(known.reshape(-1), device=dev)
+    pl = B.Plan(gd, B.HALFSPACE, precision=B.FP64, nu=nu, mu=mu)
+    pl.solve(bct, kt, tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, inf = pl.solve(bct, kt, tol=1e-6)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pz = x.cpu().numpy().reshape(3, gd.m)[2]
+    ex = p0 * np.sqrt(np.clip(1 - rr / a ** 2, 0, None))
+    inner = rr < (0.8 * a) ** 2
+    out["hertz_disc_solve_fp64"] = {"nodes": gd.m, "seconds": dt, "iters": inf["iters"],
+                                    "true_relres": inf["true_relres"],
+                                    "pressure_err_inner": float(np.abs(pz[inner] - ex[inner]).max() / p0),
+                                    "force_ratio": float(np.sum(pz * gd.weights) / (2 * np.pi * a * a * p0 / 3))}
+    pl.close()
+    out["nodes_full_surface"] = g.m
+    return out
+
+
 def timed_applies(plan, q, u, r, steps, warmup):
     import torch
 
@@ -395,6 +442,8 @@ def main():
     ap.add_argument("--no-navier", action="store_true", help="skip the 192^3 Navier star workload")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the mixed cube solves to 1e-6 (FP64 and FP32 plans), 3 each (for profilers)")
+    ap.add_argument("--halfspace-only", action="store_true",
+                    help="only the elastic half-space workload (256^2 surface, Hertz contact)")
     ap.add_argument("--cg-only", action="store_true",
                     help="only the Dirichlet CG vs GMRES solves (2D square, 3D sphere)")
     ap.add_argument("--grid-eval-only", action="store_true",
@@ -434,6 +483,9 @@ def main():
         return
     if args.learned:
         print(json.dumps(bench_learned(B, args)), flush=True)
+        return
+    if args.halfspace_only:
+        print(json.dumps(bench_halfspace(B, I, dev, args.steps)), flush=True)
         return
     if args.cg_only:
         print(json.dumps(bench_dirichlet_cg(B, I, dev)), flush=True)
@@ -547,6 +599,7 @@ def main():
                                            "status": si["status"]}
         extra["time_to_solve_1e-6"] = solves
         extra["dirichlet_cg_vs_gmres"] = bench_dirichlet_cg(B, I, dev)
+        extra["halfspace_256sq"] = bench_halfspace(B, I, dev, max(20, args.steps // 4))
         extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
         if not args.no_navier:
             print("  navier star 192^3 ...", file=sys.stderr, flush=True)

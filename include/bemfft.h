@@ -58,8 +58,29 @@ extern "C" {
 
 typedef struct bemfft_plan bemfft_plan; /* opaque; owns all device state */
 
-/* Kernel families: eq. (3) Laplace 2D, its 3D analogue, eq. (7) Kelvin. */
-typedef enum { BEMFFT_LAPLACE2D = 0, BEMFFT_LAPLACE3D = 1, BEMFFT_NAVIER3D = 2 } bemfft_kernel;
+/* Kernel families: eq. (3) Laplace 2D, its 3D analogue, eq. (7) Kelvin, and
+ * the elastic half-space of eq. (9).
+ *
+ * BEMFFT_HALFSPACE: the surface convolution of contact mechanics that the
+ * paper starts from (eq. 9, Fig. 1).  The grid is 2D and is the half-space
+ * surface; nodes are surface points (normals are ignored and may be NULL;
+ * weights default to the cell area h^2).  Per node, q holds the surface
+ * traction sigma = (sigma_x, sigma_y, sigma_z) and u the surface
+ * displacement, both [3][m] with z pointing into the solid (a compressive
+ * pressure is sigma_z > 0).  K is the Boussinesq-Cerruti tensor of the
+ * surface displacement due to a surface point load (the paper cites it and
+ * does not print it; nu = Poisson ratio, mu = shear modulus):
+ *   K_xx = g ((1 - nu)/r + nu x^2/r^3),  K_yy likewise with y,  K_xy = g nu x y / r^3,
+ *   K_zz = g (1 - nu)/r,  K_xz = -K_zx = -g (1 - 2 nu) x / (2 r^2),
+ *   K_yz = -K_zy = -g (1 - 2 nu) y / (2 r^2),  g = 1 / (2 pi mu),
+ * at the offset (x, y) = target - source, with the mean over the node's own
+ * cell at offset 0 (constant load per cell).  bemfft_apply returns
+ *   r = K[sigma] - u   (the free term is c = -1 whatever the c_mode),
+ * so K[sigma] is apply(sigma, 0), and bemfft_solve with bc = 0 finds the
+ * traction for a given displacement (a punch of known shape on a known
+ * contact area), bc = 1 the displacement for a given traction.  The 2D grid
+ * box of bemfft_eval_grid holds K[sigma] at every surface grid point. */
+typedef enum { BEMFFT_LAPLACE2D = 0, BEMFFT_LAPLACE3D = 1, BEMFFT_NAVIER3D = 2, BEMFFT_HALFSPACE = 3 } bemfft_kernel;
 
 /* Arithmetic of the transforms and the spectral product.  Kernel spectra are
  * always computed in FP64 and rounded to the working precision. */

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbemfft.so")
 
-LAPLACE2D, LAPLACE3D, NAVIER3D = 0, 1, 2
+LAPLACE2D, LAPLACE3D, NAVIER3D, HALFSPACE = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 C_HALF, C_USER, C_IMPLICIT = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBREAKDOWN, ENOCONV = 0, -1, -2, -3, -4, -5, 1
@@ -173,8 +173,11 @@ def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.
         g.pad[a] = int(pad[a]) if a < len(pad) else 0
     g.h = float(h)
     nodes = np.ascontiguousarray(nodes, dtype=np.float64)
-    normals = np.ascontiguousarray(normals, dtype=np.float64)
     m = nodes.shape[0]
+    nptr = None
+    if normals is not None:
+        normals = np.ascontiguousarray(normals, dtype=np.float64)
+        nptr = normals.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     wptr = None
     if weights is not None:
         weights = np.ascontiguousarray(weights, dtype=np.float64)
@@ -191,7 +194,7 @@ def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.
     h_ = ctypes.c_void_p()
     st = L.bemfft_plan_create(ctypes.byref(h_), ctypes.byref(g), m,
                               nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                              normals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wptr, kernel,
+                              nptr, wptr, kernel,
                               float(nu), float(mu), ctypes.byref(opts))
     _check(st, "bemfft_plan_create")
     return h_
@@ -268,7 +271,7 @@ class Plan:
     def __init__(self, geom, kernel, precision=FP64, c_mode=C_IMPLICIT, c_user=None, nu=0.3, mu=1.0,
                  pad=(0, 0, 0), stream=None, keep_fp64=False, autotune=0):
         self.kernel = kernel
-        self.ncomp = 3 if kernel == NAVIER3D else 1
+        self.ncomp = 3 if kernel in (NAVIER3D, HALFSPACE) else 1
         self.m = int(np.asarray(geom.weights).shape[0])
         self.handle = bemfft_plan_create(geom.dim, geom.n, geom.h, geom.nodes, geom.normals, geom.weights,
                                          kernel, nu, mu, origin=geom.origin, pad=pad, precision=precision,
@@ -295,7 +298,9 @@ class Plan:
         elif out.dtype != torch.float64 or out.numel() != int(np.prod(shape)):
             raise ValueError(f"eval_grid: out needs {shape} float64 values")
         bemfft_eval_grid(self.handle, q, u, out, stream)
-        return out[0, 0] if inf["dim"] == 2 else out
+        if inf["dim"] == 2:
+            return out[:, 0] if self.ncomp > 1 else out[0, 0]
+        return out
 
     def solve(self, bc, known, unknown=None, **kw):
         import torch

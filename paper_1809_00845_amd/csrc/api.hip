@@ -58,6 +58,20 @@ void self_blocks(int kernel, double w, const double n[3], double h, double nu, d
         k0w[0] = w * l / (kPi * h);
         return;
     }
+    if (kernel == BEMFFT_HALFSPACE) {
+        // the apply is r = K[sigma] - u, i.e. "S" = -K: blocks of -K over the
+        // node's own square of area w (int 1/r = 4 s ln(1 + sqrt 2) for side s,
+        // int x^2/r^3 = half of it) and over the reference cell h x h
+        const double g = 1.0 / (2.0 * kPi * mu);
+        const double a = 4.0 * std::sqrt(w) * l * g, aref = 4.0 * l / h * w * g;
+        const double dg[3] = {1.0 - 0.5 * nu, 1.0 - 0.5 * nu, 1.0 - nu};
+        for (int i = 0; i < 9; ++i) self[i] = k0w[i] = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            self[4 * k] = -a * dg[k];
+            k0w[4 * k] = -aref * dg[k];
+        }
+        return;
+    }
     const double pre = 1.0 / (16.0 * kPi * mu * (1.0 - nu));
     const double i1 = 4.0 * std::sqrt(w) * l;
     const double i1ref = 4.0 * l / h;  // per unit measure
@@ -194,6 +208,7 @@ int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double 
     a.r = r;
     if (p->kernel == 0) return apply_kind<0>(e.precision, a, st, ev);
     if (p->kernel == 1) return apply_kind<1>(e.precision, a, st, ev);
+    if (p->kernel == 3) return apply_kind<3>(e.precision, a, st, ev);
     return apply_kind<2>(e.precision, a, st, ev);
 }
 
@@ -269,14 +284,15 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
                      const double *normals, const double *weights, int kernel, double nu, double mu,
                      const bemfft_plan_opts *opts) {
     auto t0 = std::chrono::steady_clock::now();
-    if (kernel < 0 || kernel > 2) { set_error("unknown kernel"); return BEMFFT_EINVAL; }
+    if (kernel < 0 || kernel > 3) { set_error("unknown kernel"); return BEMFFT_EINVAL; }
+    const bool halfspace = kernel == BEMFFT_HALFSPACE;
     KindInfo ki = kind_info(kernel);
     if (grid->dim != ki.dim) { set_error("grid dimension does not match the kernel"); return BEMFFT_EINVAL; }
     if (m < 1 || m > (int64_t)1 << 30) { set_error("node count out of range"); return BEMFFT_EINVAL; }
-    if (!nodes || !normals) { set_error("nodes and normals are required"); return BEMFFT_EINVAL; }
+    if (!nodes || (!normals && !halfspace)) { set_error("nodes and normals are required"); return BEMFFT_EINVAL; }
     if (!(grid->h > 0.0) || !std::isfinite(grid->h)) { set_error("grid spacing must be positive"); return BEMFFT_EINVAL; }
-    if (kernel == BEMFFT_NAVIER3D && (!(nu > -1.0 && nu < 0.5) || !(mu > 0.0))) {
-        set_error("Navier needs nu in (-1, 1/2) and mu > 0");
+    if ((kernel == BEMFFT_NAVIER3D || halfspace) && (!(nu > -1.0 && nu < 0.5) || !(mu > 0.0))) {
+        set_error("elasticity needs nu in (-1, 1/2) and mu > 0");
         return BEMFFT_EINVAL;
     }
     const int prec = opts ? (int)opts->precision : BEMFFT_FP64;
@@ -321,7 +337,7 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     for (int64_t j = 0; j < m; ++j) {
         for (int a = 0; a < d; ++a) {
             const double x = nodes[j * d + a];
-            const double nv = normals[j * d + a];
+            const double nv = normals ? normals[j * d + a] : 0.0;
             if (!std::isfinite(x) || !std::isfinite(nv)) { set_error("non-finite node or normal"); return BEMFFT_EINVAL; }
             const double gi = std::floor((x - p->origin[a]) / p->h + 0.5);
             if (gi < 0.0 || gi >= (double)p->n[a]) {
@@ -331,7 +347,9 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
             g[j * 3 + a] = (int)gi;
             nr[j * 3 + a] = nv;
         }
-        w[j] = weights ? weights[j] : std::pow(p->h, d - 1);
+        // default measure: the grid's line or surface element (the half-space
+        // grid is the surface itself: h^2)
+        w[j] = weights ? weights[j] : (halfspace ? p->h * p->h : std::pow(p->h, d - 1));
         if (!(w[j] > 0.0) || !std::isfinite(w[j])) { set_error("weights must be positive and finite"); return BEMFFT_EINVAL; }
     }
     // sort by (z, y, x): rows of the grid become contiguous runs
@@ -404,7 +422,11 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     if (status) { free_engine(&e64); return status; }
     // free term
     std::vector<double> Cs;
-    if (cmode == BEMFFT_C_IMPLICIT) {
+    if (halfspace) {  // r = K[sigma] - u for every mode
+        Cs.assign((size_t)m * O * O, 0.0);
+        for (int64_t s = 0; s < m; ++s)
+            for (int k = 0; k < O; ++k) Cs[((size_t)s * O + k) * O + k] = -1.0;
+    } else if (cmode == BEMFFT_C_IMPLICIT) {
         status = implicit_free_term(p, e64, st, Cs);
         if (status) { free_engine(&e64); return status; }
     } else {
@@ -625,6 +647,7 @@ int bemfft_eval_grid(bemfft_plan *p, const double *q, const double *u, double *o
     hipStream_t st = (hipStream_t)stream;
     if (p->kernel == 0) return volume_kind<0>(p->eng.precision, a, out, st, nullptr);
     if (p->kernel == 1) return volume_kind<1>(p->eng.precision, a, out, st, nullptr);
+    if (p->kernel == 3) return volume_kind<3>(p->eng.precision, a, out, st, nullptr);
     return volume_kind<2>(p->eng.precision, a, out, st, nullptr);
 }
 

@@ -86,7 +86,7 @@ __device__ __forceinline__ int mod_small(int kx, int x, int p, float inv_p) {
 // ------------------------------------------------------------------ k_fields
 // Boundary fields of every node in sorted order (the zero-extended data of
 // Fig. 4 before it is placed on the grid): Laplace q w and u n_i w;
-// Navier t_j w and the symmetrised u (x) n w.
+// Navier t_j w and the symmetrised u (x) n w; half-space sigma_b w.
 template <typename R, int KIND>
 __device__ __forceinline__ void fields_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
     const int s = bx * 256 + threadIdx.x;
@@ -95,7 +95,10 @@ __device__ __forceinline__ void fields_body(const ApplyArgs &a, const int bx, co
     const int j = a.perm[s];
     const double wt = a.w[s];
     const double n[3] = {a.nrm[s], a.nrm[a.m + s], a.nrm[2 * a.m + s]};
-    if constexpr (KIND == 0 || KIND == 1) {
+    if constexpr (KIND == 3) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vf[c * a.m + s] = (R)(a.q[c * a.m + j] * wt);
+    } else if constexpr (KIND == 0 || KIND == 1) {
         const double uw = a.u[j] * wt;
         vf[s] = (R)(a.q[j] * wt);
 #pragma unroll
@@ -859,7 +862,7 @@ struct Launch {
         }
         BF_CHECK(s3);
         int s4 = BEMFFT_EUNSUPPORTED;
-        if constexpr (KIND == 0) {
+        if constexpr (KIND == 0 || KIND == 3) {
             if (g.pz == 1) s4 = bz_s<1, 0>(dm, io, g, st);
         } else {
             switch (g.pz) {
@@ -909,7 +912,7 @@ struct Launch {
         return BEMFFT_EUNSUPPORTED;
     }
     static int dispatch_z(const ApplyArgs &a, hipStream_t st) {
-        if constexpr (KIND == 0) {
+        if constexpr (KIND == 0 || KIND == 3) {
             if (a.pz == 1) return launch_z<R, 1, KIND, 0>(a, st);
             set_error("2D plans need pz == 1");
             return BEMFFT_EUNSUPPORTED;

@@ -72,6 +72,7 @@ int launch_groups(bemfft_batch *b, hipStream_t st) {
         int s;
         if (g.kernel == 0) s = apply_batch_kind<0>(g.precision, g.d_args, b->d_io, g.dims, st);
         else if (g.kernel == 1) s = apply_batch_kind<1>(g.precision, g.d_args, b->d_io, g.dims, st);
+        else if (g.kernel == 3) s = apply_batch_kind<3>(g.precision, g.d_args, b->d_io, g.dims, st);
         else s = apply_batch_kind<2>(g.precision, g.d_args, b->d_io, g.dims, st);
         BF_CHECK(s);
     }

@@ -35,6 +35,8 @@ void set_error(const std::string &msg);
 //   Laplace 3D: fields q w, u n_i w (3);      spectra u*, d_i u* (3).
 //   Navier:     fields t_j w (3), s_(ij) w (6, symmetric u (x) n);
 //               spectra U_(kj) (6), Sigma_k,(ij) (18).
+//   Half-space: fields sigma_b w (3); spectra K_xx, K_yy, K_xy, K_zz, K_xz,
+//               K_yz, K_zx, K_zy (Boussinesq-Cerruti, eq. 9).
 struct KindInfo {
     int dim, ncomp, F, K, O;
 };
@@ -42,6 +44,7 @@ inline KindInfo kind_info(int kernel) {
     switch (kernel) {
         case BEMFFT_LAPLACE2D: return {2, 1, 3, 3, 1};
         case BEMFFT_LAPLACE3D: return {3, 1, 4, 4, 1};
+        case BEMFFT_HALFSPACE: return {2, 3, 3, 8, 3};
         default: return {3, 3, 9, 24, 3};
     }
 }

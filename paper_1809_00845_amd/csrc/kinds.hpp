@@ -9,6 +9,11 @@
 //   Navier:   - sum_j U_kj * (t_j w) - sum_(ij) Sigma_k,(ij) * s_(ij)
 // so every spectrum is stored with the factor -1 (and 1/(Px Py Pz)) folded in
 // and each output is a plain sum of products.
+//
+// The elastic half-space (eq. 9) is a convolution already: the surface
+// displacement is u_a = sum_b K_ab * (sigma_b w) with the Boussinesq-Cerruti
+// tensor K; its spectra carry +1/(Px Py) and the plan's free term c = -1
+// turns the apply into r = K[sigma] - u.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +31,10 @@ __host__ __device__ constexpr int pair_of(int i, int j) {
 // kernel that is even/odd per axis is real when the number of odd axes is
 // even and imaginary when it is odd; it keeps each axis' parity in k.
 __host__ __device__ constexpr int comp_oddmask(int kernel, int c) {
+    if (kernel == 3) {  // xx, yy, xy, zz, xz, yz, zx, zy
+        constexpr int m[8] = {0, 0, 3, 0, 1, 2, 1, 2};
+        return m[c];
+    }
     if (kernel == 0) return c == 0 ? 0 : (1 << (c - 1));
     if (kernel == 1) return c == 0 ? 0 : (1 << (c - 1));
     if (c < 6) return (1 << pair_i(c)) ^ (1 << pair_j(c));
@@ -62,6 +71,17 @@ struct Terms<2> {  // Navier (Kelvin): 27 terms, 3 per field, ordered by field
     __host__ __device__ static constexpr int o(int t) { return t % 3; }
     __host__ __device__ static constexpr int c(int t) {
         return f(t) < 3 ? pair_of(o(t), f(t)) : 6 + 6 * o(t) + (f(t) - 3);
+    }
+};
+
+template <>
+struct Terms<3> {  // elastic half-space: u_a = sum_b K_ab * sigma_b, 9 terms
+    static constexpr int F = 3, O = 3, K = 8, N = 9;
+    __host__ __device__ static constexpr int f(int t) { return t % 3; }
+    __host__ __device__ static constexpr int o(int t) { return t / 3; }
+    __host__ __device__ static constexpr int c(int t) {
+        constexpr int tab[9] = {0, 2, 4, 2, 1, 5, 6, 7, 3};  // (o, f) row-major
+        return tab[t];
     }
 };
 

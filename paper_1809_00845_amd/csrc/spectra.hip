@@ -39,6 +39,21 @@ __device__ double kernel_value(int kernel, int c, double x, double y, double z, 
         double a = (c == 1) ? x : ((c == 2) ? y : z);
         return -a / (4.0 * kPi * r2 * r);
     }
+    if (kernel == BEMFFT_HALFSPACE) {
+        // surface displacement a at offset (x, y) from a unit surface point
+        // load b (Boussinesq for b = z, Cerruti for b = x, y), z into the solid
+        const double g = 1.0 / (2.0 * kPi * mu);
+        switch (c) {
+            case 0: return g * ((1.0 - nu) / r + nu * x * x / (r2 * r));  // xx
+            case 1: return g * ((1.0 - nu) / r + nu * y * y / (r2 * r));  // yy
+            case 2: return g * nu * x * y / (r2 * r);                     // xy
+            case 3: return g * (1.0 - nu) / r;                            // zz
+            case 4: return -g * 0.5 * (1.0 - 2.0 * nu) * x / r2;          // xz
+            case 5: return -g * 0.5 * (1.0 - 2.0 * nu) * y / r2;          // yz
+            case 6: return g * 0.5 * (1.0 - 2.0 * nu) * x / r2;           // zx
+            default: return g * 0.5 * (1.0 - 2.0 * nu) * y / r2;          // zy
+        }
+    }
     double xi[3] = {x, y, z};
     if (c < 6) {  // Kelvin displacement tensor, eq. (7)
         int k = pair_i(c), j = pair_j(c);
@@ -61,6 +76,13 @@ double kernel_k0(int kernel, int c, double h, double nu, double mu) {
     const double l = std::log(1.0 + std::sqrt(2.0));
     if (kernel == BEMFFT_LAPLACE2D) return c == 0 ? (1.0 - std::log(0.5 * h)) / (2.0 * kPi) : 0.0;
     if (kernel == BEMFFT_LAPLACE3D) return c == 0 ? l / (kPi * h) : 0.0;
+    if (kernel == BEMFFT_HALFSPACE) {
+        // mean over the h x h cell: <1/r> = 4 ln(1 + sqrt 2) / h, <x^2/r^3> = <1/r> / 2
+        const double a0 = 4.0 * l / h / (2.0 * kPi * mu);
+        if (c == 0 || c == 1) return a0 * (1.0 - 0.5 * nu);
+        if (c == 3) return a0 * (1.0 - nu);
+        return 0.0;
+    }
     if (c < 3) return (4.0 * l / h) * ((3.0 - 4.0 * nu) + 1.0 / 3.0) / (16.0 * kPi * mu * (1.0 - nu));
     return 0.0;
 }
@@ -232,7 +254,7 @@ int build_spectra(bemfft_plan *p, Engine *e64, Engine *e32, hipStream_t st) {
     }
     double worst = 0.0;
     int status = 0;
-    const double scale = -1.0 / (double)full_n;
+    const double scale = (p->kernel == BEMFFT_HALFSPACE ? 1.0 : -1.0) / (double)full_n;
     for (int c = 0; c < p->K && status == 0; ++c) {
         double k0 = kernel_k0(p->kernel, c, p->h, p->nu, p->mu);
         int blocks = (int)std::min<int64_t>((full_n + 255) / 256, 65536);

@@ -13,7 +13,8 @@
 //            and kx = Px/2 dropped, as the node gather does) and packed as
 //            A + iB; one inverse complex FFT of length Px then holds row a
 //            in its real and row b in its imaginary part.  x < nx is kept,
-//            negated (the grid holds D[u] - S[q]).
+//            negated (the grid holds D[u] - S[q]; for the half-space it
+//            holds K[sigma], kept as it is).
 //                                                -> out[o][z][y][x] (FP64)
 //
 // W reuses the forward intermediate Y, free once the z pass has run:
@@ -37,7 +38,7 @@ struct VolXCfg {
 // W: [nrows][hx] half spectra; out: [nrows][nx].
 template <typename R, int PX>
 __global__ __launch_bounds__((VolXCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__restrict__ W, const cx<R> *twx,
-                                                                 int hx, int nx, int64_t nrows,
+                                                                 int hx, int nx, int64_t nrows, double sign,
                                                                  double *__restrict__ out) {
     using Cfg = VolXCfg<R, PX>;
     constexpr int TPP = Cfg::TPP, PS = Cfg::PS, PPB = Cfg::PPB, NT = Cfg::NT, E = PX / TPP;
@@ -73,8 +74,8 @@ __global__ __launch_bounds__((VolXCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__r
     for (int e = 0; e < E / 2; ++e) {  // nx <= Px/2
         const int xg = t + e * TPP;
         if (xg < nx) {
-            if (va) out[ra * nx + xg] = -(double)x[e].x;
-            if (vb) out[rb * nx + xg] = -(double)x[e].y;
+            if (va) out[ra * nx + xg] = sign * (double)x[e].x;
+            if (vb) out[rb * nx + xg] = sign * (double)x[e].y;
         }
     }
 }
@@ -88,7 +89,7 @@ struct VolumeLaunch {
         const int64_t nb = (nrows + 2 * Cfg::PPB - 1) / (2 * Cfg::PPB);
         hipLaunchKernelGGL((k_vol_x<R, P>), dim3((unsigned)nb), dim3(Cfg::NT), 0, st,
                            static_cast<const cx<R> *>(a.Y), static_cast<const cx<R> *>(a.twx), a.hx, a.nx, nrows,
-                           out);
+                           KIND == 3 ? 1.0 : -1.0, out);
         BF_HIP(hipGetLastError());
         return 0;
     }

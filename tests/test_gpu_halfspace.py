@@ -1,0 +1,125 @@
+"""GPU parity of the elastic half-space (eq. 9): r = K[sigma] - u through
+the C ABI against the oracle's direct sum, the grid-box displacement, and
+the frictionless Hertz contact solved on the GPU.
+
+Bar as for the boundary operator (normwise against the oracle's sum of term
+magnitudes): 1e-12 in FP64, 2e-5 in FP32.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_1809_00845_amd import binding as B  # noqa: E402
+from paper_1809_00845_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.FP64: 1e-12, B.FP32: 2e-5}
+NU, MU = 0.3, 1.0
+E = 2 * MU * (1 + NU)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), device=dev)
+
+
+def _parity(dev, g, precision, seed=0, targets=None):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(-1, 1, (3, g.m))
+    u = rng.uniform(-1, 1, (3, g.m))
+    plan = B.Plan(g, B.HALFSPACE, precision=precision, nu=NU, mu=MU)
+    r = plan.apply(_t(q, dev), _t(u, dev)).cpu().numpy().reshape(3, g.m)
+    p = O.problem(g, O.HALFSPACE, NU, MU)
+    ref, sc = O.apply(p, q, u, with_scale=True, targets=targets)
+    t0, t1 = targets or (0, g.m)
+    err = np.abs(r[:, t0:t1] - ref).max() / np.max(sc)
+    info = plan.info()
+    plan.close()
+    return err, info
+
+
+@pytest.mark.parametrize("precision", [B.FP64, B.FP32])
+@pytest.mark.parametrize("case", ["disc64", "full48"])
+def test_halfspace_apply_vs_oracle(dev, case, precision):
+    # disc: a circular contact patch (P = 128); full: every grid point, so
+    # every row is a long row transformed by FFT (P = 96)
+    g = I.halfspace_patch(64, 0.35) if case == "disc64" else I.halfspace_patch(48)
+    err, info = _parity(dev, g, precision)
+    assert info["noutputs"] == 3 and info["nspectra"] == 8
+    assert err < TOL[precision], (case, err)
+
+
+@pytest.mark.parametrize("precision", [B.FP64, B.FP32])
+def test_halfspace_full_size_sampled(dev, precision):
+    # the 256^2 surface (65,536 nodes, P = 512), first 300 targets
+    g = I.halfspace_patch(256)
+    err, info = _parity(dev, g, precision, seed=1, targets=(0, 300))
+    assert info["pad"][0] == 512 and err < TOL[precision]
+
+
+def test_halfspace_grid_displacement(dev):
+    # K[sigma] at every surface grid point, inside and outside the loaded disc
+    g = I.halfspace_patch(64, 0.3)
+    rng = np.random.default_rng(2)
+    q = rng.uniform(-1, 1, (3, g.m))
+    plan = B.Plan(g, B.HALFSPACE, precision=B.FP64, nu=NU, mu=MU)
+    out = plan.eval_grid(_t(q, dev), torch.zeros(3 * g.m, dtype=torch.float64, device=dev))
+    got = out.cpu().numpy().reshape(3, -1)
+    n = 64
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pts = np.stack([x.ravel(), y.ravel()], -1)
+    idx = rng.choice(len(pts), 300, replace=False)
+    p = O.problem(g, O.HALFSPACE, NU, MU)
+    ref, sc = O.volume(p, q, np.zeros_like(q), pts[idx], with_scale=True)
+    assert np.abs(got[:, idx] + ref).max() / np.max(sc) < 1e-12
+    plan.close()
+
+
+def _hertz(g, a, p0):
+    rr = np.sum((g.nodes - g.center) ** 2, axis=1)
+    bc = np.zeros((3, g.m), dtype=np.uint8)
+    bc[:2] = 1  # frictionless: zero shear traction given
+    known = np.zeros((3, g.m))
+    known[2] = np.pi * (1 - NU ** 2) * p0 * (2 * a ** 2 - rr) / (4 * a * E)
+    return rr, bc, known
+
+
+def test_hertz_solve_vs_oracle_lu(dev):
+    a, p0 = 0.3, 1.0
+    g = I.halfspace_patch(48, a)
+    _, bc, known = _hertz(g, a, p0)
+    ref = O.solve_lu(O.problem(g, O.HALFSPACE, NU, MU), bc, known)
+    plan = B.Plan(g, B.HALFSPACE, precision=B.FP64, nu=NU, mu=MU)
+    x, info = plan.solve(_t(bc, dev).reshape(-1), _t(known, dev).reshape(-1), tol=1e-11)
+    assert info["status"] == 0
+    x = x.cpu().numpy().reshape(3, g.m)
+    assert np.abs(x - ref).max() <= 1e-8 * np.abs(ref).max()
+    plan.close()
+
+
+def test_hertz_solve_at_full_size(dev):
+    # contact disc of radius 0.3 on the 256^2 surface (about 18,500 nodes)
+    a, p0 = 0.3, 1.0
+    g = I.halfspace_patch(256, a)
+    rr, bc, known = _hertz(g, a, p0)
+    plan = B.Plan(g, B.HALFSPACE, precision=B.FP32, nu=NU, mu=MU, keep_fp64=True)
+    x, info = plan.solve(_t(bc, dev).reshape(-1), _t(known, dev).reshape(-1), tol=1e-8, refine=1)
+    assert info["status"] == 0 and info["true_relres"] < 1e-8
+    pz = x.cpu().numpy().reshape(3, g.m)[2]
+    ex = p0 * np.sqrt(np.clip(1 - rr / a ** 2, 0, None))
+    inner = rr < (0.8 * a) ** 2
+    assert np.abs(pz[inner] - ex[inner]).max() < 3e-3 * p0
+    force = np.sum(pz * g.weights)
+    assert abs(force / (2 * np.pi * a ** 2 * p0 / 3) - 1) < 2e-3
+    plan.close()
