@@ -24,6 +24,12 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 const int64_t kSizes[] = {32, 64, 96, 128, 192, 256, 320, 384, 512};
 // A grid row holding this many nodes is x-transformed by FFT.
 constexpr int kDenseRow = 24;
+// The long rows' inverse x transform goes through a row FFT (one more launch,
+// a few microseconds) when the per-node sums it replaces exceed this many
+// complex products: the nodes of long rows x Hx x outputs.  Measured: the
+// 128^3 cube (3e6) is faster without it, the 256^2 half-space surface (5e7)
+// 1.4x faster with it.
+constexpr double kRowInvWork = 8.0e6;
 
 template <typename T>
 int dev_upload(T **dst, const std::vector<T> &src) {
@@ -176,6 +182,7 @@ void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, Ap
     a.row_dense = p->d_row_dense;
     a.dense_rows = p->d_dense_rows;
     a.nd = (int)p->nd;
+    a.row_inv = p->row_inv;
     a.zsched = p->zsched;
     a.off = 0;
     a.gid = 0;
@@ -389,6 +396,11 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
         }
     }
     p->nd = (int64_t)dense_rows.size();
+    {
+        int64_t long_nodes = 0;
+        for (int r : dense_rows) long_nodes += rowptr[r + 1] - rowptr[r];
+        p->row_inv = (double)long_nodes * (double)p->H[0] * p->O > kRowInvWork ? 1 : 0;
+    }
     // per-node free term and self correction blocks (sorted order)
     const int O = p->O;
     std::vector<double> C((size_t)m * O * O, 0.0), SC((size_t)m * O * O, 0.0);

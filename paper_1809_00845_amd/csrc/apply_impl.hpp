@@ -16,6 +16,8 @@
 //              evaluated only at its own x ("the values of interest lie only
 //              on the boundary", Sec. 4), plus c u and the self-term
 //              correction                              -> r
+//              (nodes of long rows read their row's inverse FFT, made by
+//              k_rows_inv, instead)
 //
 // Layout: complex intermediates are interleaved (re, im) in the working
 // precision R with ky contiguous, so every global access is a run of whole
@@ -51,6 +53,7 @@ struct ApplyArgs {
     const int *row_dense;   // [nzo * ny]: index into dense_rows, or -1
     const int *dense_rows;  // [nd]: row index (zz * ny + y) of each long row
     int nd;
+    int row_inv;            // 1: the long rows' inverse x transform is an FFT (k_rows_inv)
     void *Y, *Z;
 };
 
@@ -60,6 +63,7 @@ struct GroupDims {
     int nmem;
     int max_m, max_nd, max_nzo;
     int hx, px, py, pz, zsched;
+    int row_inv;  // some member takes the row FFT for its long rows
 };
 
 // Base pointers of a batched apply (device memory, so that a captured graph
@@ -599,6 +603,97 @@ __global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void kb_inv_y(const App
     inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, 0);
 }
 
+// ------------------------------------------------------------------ whole rows, inverse x
+template <typename R, int PX>
+struct RowInvCfg {
+    static constexpr int TPP = PencilShape<PX>::TPP;
+    static constexpr int CB = (int)sizeof(cx<R>);
+    static constexpr int PS = pstride<PX>();
+    static constexpr int PPB = clampi(mini(256 / TPP, (64 * 1024 - PX * CB) / (PS * CB)), 1, 64);
+    static constexpr int NT = PPB * TPP;
+};
+
+// Inverse x transform of two real rows from their half spectra Wa, Wb (Hx =
+// PX/2 + 1 coefficients; a missing row is zero): the spectra are extended to
+// Hermitian sequences A, B (imaginary parts at kx = 0 and PX/2 dropped, as
+// the node gather does) and packed as A + iB, so one complex inverse FFT of
+// length PX holds row a in its real and row b in its imaginary part.  Lane t
+// of the pencil ends with x[e] = value at t + e TPP.  tw: the LDS twiddle
+// table, already synchronised.
+template <typename R, int PX>
+__device__ __forceinline__ void inv_x_pair(const cx<R> *Wa, const cx<R> *Wb, bool va, bool vb, cx<R> *pen,
+                                           const cx<R> *tw, int t, cx<R> (&x)[PX / PencilShape<PX>::TPP]) {
+    constexpr int TPP = PencilShape<PX>::TPP, E = PX / TPP;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * TPP;
+        const bool lo = 2 * k <= PX;
+        const int kk = lo ? k : PX - k;  // kk < Hx
+        cx<R> A = va ? Wa[kk] : cx<R>{R(0), R(0)};
+        cx<R> B = vb ? Wb[kk] : cx<R>{R(0), R(0)};
+        if (kk == 0 || 2 * kk == PX) {
+            A.y = R(0);
+            B.y = R(0);
+        }
+        if (!lo) {  // Hermitian extension: conj of the mirrored coefficient
+            A.y = -A.y;
+            B.y = -B.y;
+        }
+        x[e] = {A.x - B.y, A.y + B.x};  // A + iB
+    }
+    fft_regs<R, PX, 1>(x, pen, tw, t);
+}
+
+// Long rows (those whose forward x transform was an FFT) get their inverse x
+// transform by FFT too: row (d, o) of W -> Xr[d][o][x], x < nx, in the
+// buffer of the forward row transforms (free after the forward pass).  The
+// gather then reads their nodes' values instead of summing the row's
+// spectrum once per node.
+template <typename R, int PX, int KIND>
+__device__ __forceinline__ void rows_inv_body(const ApplyArgs &a, const int bx) {
+    using Cfg = RowInvCfg<R, PX>;
+    constexpr int O = Terms<KIND>::O, TPP = Cfg::TPP, PS = Cfg::PS, PPB = Cfg::PPB, NT = Cfg::NT, E = PX / TPP;
+    __shared__ cx<R> buf[PPB * PS];
+    __shared__ cx<R> tw[PX];
+    const int nrows = a.row_inv ? a.nd * O : 0;
+    if (bx * PPB * 2 >= nrows) return;  // block-uniform: batched members with fewer long rows
+    const int tid = threadIdx.x;
+    const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
+    for (int i = tid; i < PX; i += NT) tw[i] = gtwx[i];
+    __syncthreads();
+    const int pen = tid / TPP, t = tid % TPP;
+    const int ra = (bx * PPB + pen) * 2, rb = ra + 1;
+    const bool va = ra < nrows, vb = rb < nrows;
+    const cx<R> *W = static_cast<const cx<R> *>(a.Y);
+    const size_t ostride = (size_t)a.nzo * a.ny;  // rows of W per output
+    const cx<R> *Wa = W + ((size_t)(ra % O) * ostride + (va ? a.dense_rows[ra / O] : 0)) * a.hx;
+    const cx<R> *Wb = W + ((size_t)(rb % O) * ostride + (vb ? a.dense_rows[rb / O] : 0)) * a.hx;
+    cx<R> x[E];
+    inv_x_pair<R, PX>(Wa, Wb, va, vb, buf + pen * PS, tw, t, x);
+    R *Xr = static_cast<R *>(a.Xd);
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {  // nx <= Px/2
+        const int xg = t + e * TPP;
+        if (xg < a.nx) {
+            if (va) Xr[(size_t)ra * a.nx + xg] = x[e].x;
+            if (vb) Xr[(size_t)rb * a.nx + xg] = x[e].y;
+        }
+    }
+}
+
+template <typename R, int PX, int KIND>
+__global__ __launch_bounds__((RowInvCfg<R, PX>::NT)) void k_rows_inv(ApplyArgs a) {
+    rows_inv_body<R, PX, KIND>(a, blockIdx.x);
+}
+
+// Batched form: blockIdx.z = member.
+template <typename R, int PX, int KIND>
+__global__ __launch_bounds__((RowInvCfg<R, PX>::NT)) void kb_rows_inv(const ApplyArgs *members, const BatchIO *io) {
+    const ApplyArgs &a = members[blockIdx.z];
+    if (io->active && !io->active[a.gid]) return;
+    rows_inv_body<R, PX, KIND>(a, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ k_gather
 // Eight lanes per node: the inverse x transform of the node's row in W,
 //   sum_kx cf Re(W[kx] exp(+2 pi i kx x / Px)),  cf = 1 at kx = 0 and Px/2,
@@ -620,6 +715,23 @@ __device__ __forceinline__ void gather_body(const ApplyArgs &a, const int bx) {
     const int s = bx * (256 / L) + threadIdx.x / L;
     if (s >= a.m) return;  // the node's eight lanes leave together
     const int zz = a.gz[s] - a.z0, y = a.gy[s], xg = a.gx[s];
+    const int dr = a.row_inv ? a.row_dense[zz * a.ny + y] : -1;
+    if (dr >= 0) {  // a long row: its values come from the row FFT
+        if (sub != 0) return;
+        const R *Xr = static_cast<const R *>(a.Xd);
+        const int j = a.perm[s];
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            double v = (double)Xr[((size_t)dr * O + o) * a.nx + xg];
+#pragma unroll
+            for (int l = 0; l < O; ++l) {
+                v += a.C[((size_t)s * O + o) * O + l] * a.u[l * a.m + j];
+                v -= a.SC[((size_t)s * O + o) * O + l] * a.q[l * a.m + j];
+            }
+            a.r[o * a.m + j] = v;
+        }
+        return;
+    }
     const int hx = a.hx, px = a.px;
     const size_t rstride = (size_t)a.nzo * a.ny * hx;  // between outputs
     const cx<R> *row = static_cast<const cx<R> *>(a.Y) + ((size_t)zz * a.ny + y) * hx;
@@ -750,6 +862,25 @@ struct Launch {
         BF_HIP(hipGetLastError());
         return 0;
     }
+    template <int P> static int rows_inv(const ApplyArgs &a, hipStream_t st) {
+        using Cfg = RowInvCfg<R, P>;
+        const int nb = (a.nd * Terms<KIND>::O + 2 * Cfg::PPB - 1) / (2 * Cfg::PPB);
+        hipLaunchKernelGGL((k_rows_inv<R, P, KIND>), dim3(nb), dim3(Cfg::NT), 0, st, a);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    template <int P> static int brows_inv(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
+        using Cfg = RowInvCfg<R, P>;
+        const int nb = (g.max_nd * Terms<KIND>::O + 2 * Cfg::PPB - 1) / (2 * Cfg::PPB);
+        hipLaunchKernelGGL((kb_rows_inv<R, P, KIND>), dim3(nb, 1, g.nmem), dim3(Cfg::NT), 0, st, dm, io);
+        BF_HIP(hipGetLastError());
+        return 0;
+    }
+    static int dispatch_rows_inv(const ApplyArgs &a, hipStream_t st) {
+        BF_SIZE_SWITCH(a.px, rows_inv, a, st);
+        set_error("unsupported x length");
+        return BEMFFT_EUNSUPPORTED;
+    }
     template <int P> static int inv_y(const ApplyArgs &a, int all_rows, hipStream_t st) {
         return launch_inv_y<R, P, KIND>(a, all_rows, st);
     }
@@ -778,6 +909,7 @@ struct Launch {
         BF_CHECK(front(a, st, ev));
         BF_CHECK(dispatch_inv_y(a, 0, st));
         if (ev) BF_HIP(hipEventRecord(ev[3], st));
+        if (a.nd > 0 && a.row_inv) BF_CHECK(dispatch_rows_inv(a, st));
         constexpr int NPB = 256 / kGatherLanes;  // nodes per block
         hipLaunchKernelGGL((k_gather<R, KIND>), dim3((a.m + NPB - 1) / NPB), dim3(256), 0, st, a);
         BF_HIP(hipGetLastError());
@@ -893,6 +1025,22 @@ struct Launch {
             default: break;
         }
         BF_CHECK(s5);
+        if (g.max_nd > 0 && g.row_inv) {
+            int s6 = BEMFFT_EUNSUPPORTED;
+            switch (g.px) {
+                case 32: s6 = brows_inv<32>(dm, io, g, st); break;
+                case 64: s6 = brows_inv<64>(dm, io, g, st); break;
+                case 96: s6 = brows_inv<96>(dm, io, g, st); break;
+                case 128: s6 = brows_inv<128>(dm, io, g, st); break;
+                case 192: s6 = brows_inv<192>(dm, io, g, st); break;
+                case 256: s6 = brows_inv<256>(dm, io, g, st); break;
+                case 320: s6 = brows_inv<320>(dm, io, g, st); break;
+                case 384: s6 = brows_inv<384>(dm, io, g, st); break;
+                case 512: s6 = brows_inv<512>(dm, io, g, st); break;
+                default: break;
+            }
+            BF_CHECK(s6);
+        }
         constexpr int NPB = 256 / kGatherLanes;  // nodes per block
         hipLaunchKernelGGL((kb_gather<R, KIND>), dim3((g.max_m + NPB - 1) / NPB, 1, g.nmem), dim3(256), 0, st, dm, io);
         BF_HIP(hipGetLastError());

@@ -348,7 +348,7 @@ int bemfft_batch_create(bemfft_batch **out, bemfft_plan *const *plans, int nplan
             Group g;
             g.kernel = b->kernel;
             g.precision = b->precision;
-            g.dims = GroupDims{0, 0, 0, 0, (int)p->H[0], (int)p->P[0], (int)p->P[1], (int)p->P[2], p->zsched};
+            g.dims = GroupDims{0, 0, 0, 0, (int)p->H[0], (int)p->P[0], (int)p->P[1], (int)p->P[2], p->zsched, 0};
             gidx[key] = (int)b->groups.size();
             b->groups.push_back(g);
             it = gidx.find(key);
@@ -359,6 +359,7 @@ int bemfft_batch_create(bemfft_batch **out, bemfft_plan *const *plans, int nplan
         g.dims.max_m = std::max<int>(g.dims.max_m, (int)p->m);
         g.dims.max_nd = std::max<int>(g.dims.max_nd, (int)p->nd);
         g.dims.max_nzo = std::max<int>(g.dims.max_nzo, (int)p->nzo);
+        g.dims.row_inv = std::max(g.dims.row_inv, p->row_inv);
     }
     for (auto &g : b->groups) {
         if (status) break;

@@ -8,11 +8,10 @@
 //
 //   k_inv_y  (the apply's own) inverse y-FFT of every output, rows y < ny
 //            written with kx contiguous            -> W[o][z][y][kx]  (in Y)
-//   k_vol_x  two grid rows per pencil: the half spectra of rows a and b are
-//            extended to Hermitian sequences A, B (imaginary parts at kx = 0
-//            and kx = Px/2 dropped, as the node gather does) and packed as
-//            A + iB; one inverse complex FFT of length Px then holds row a
-//            in its real and row b in its imaginary part.  x < nx is kept,
+//   k_vol_x  two grid rows per pencil through inv_x_pair (the half spectra
+//            of rows a and b packed as A + iB of their Hermitian extensions;
+//            one inverse complex FFT of length Px holds row a in its real and
+//            row b in its imaginary part).  x < nx is kept,
 //            negated (the grid holds D[u] - S[q]; for the half-space it
 //            holds K[sigma], kept as it is).
 //                                                -> out[o][z][y][x] (FP64)
@@ -26,50 +25,24 @@
 namespace bemfft {
 
 // ------------------------------------------------------------------ k_vol_x
+// W: [nrows][hx] half spectra; out: [nrows][nx].  Two rows per pencil
+// (inv_x_pair), times sign.
 template <typename R, int PX>
-struct VolXCfg {
-    static constexpr int TPP = PencilShape<PX>::TPP;
-    static constexpr int CB = (int)sizeof(cx<R>);
-    static constexpr int PS = pstride<PX>();
-    static constexpr int PPB = clampi(mini(256 / TPP, (64 * 1024 - PX * CB) / (PS * CB)), 1, 64);
-    static constexpr int NT = PPB * TPP;
-};
-
-// W: [nrows][hx] half spectra; out: [nrows][nx].
-template <typename R, int PX>
-__global__ __launch_bounds__((VolXCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__restrict__ W, const cx<R> *twx,
-                                                                 int hx, int nx, int64_t nrows, double sign,
-                                                                 double *__restrict__ out) {
-    using Cfg = VolXCfg<R, PX>;
+__global__ __launch_bounds__((RowInvCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__restrict__ W, const cx<R> *twx,
+                                                                   int hx, int nx, int64_t nrows, double sign,
+                                                                   double *__restrict__ out) {
+    using Cfg = RowInvCfg<R, PX>;
     constexpr int TPP = Cfg::TPP, PS = Cfg::PS, PPB = Cfg::PPB, NT = Cfg::NT, E = PX / TPP;
     __shared__ cx<R> buf[PPB * PS];
     __shared__ cx<R> tw[PX];
     const int tid = threadIdx.x;
     for (int i = tid; i < PX; i += NT) tw[i] = twx[i];
+    __syncthreads();  // twiddle table
     const int pen = tid / TPP, t = tid % TPP;
     const int64_t ra = ((int64_t)blockIdx.x * PPB + pen) * 2, rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
-    const cx<R> *Wa = W + ra * hx, *Wb = W + rb * hx;
     cx<R> x[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = t + e * TPP;
-        const bool lo = 2 * k <= PX;
-        const int kk = lo ? k : PX - k;  // kk < hx
-        cx<R> A = va ? Wa[kk] : cx<R>{R(0), R(0)};
-        cx<R> B = vb ? Wb[kk] : cx<R>{R(0), R(0)};
-        if (kk == 0 || 2 * kk == PX) {
-            A.y = R(0);
-            B.y = R(0);
-        }
-        if (!lo) {  // Hermitian extension: conj of the mirrored coefficient
-            A.y = -A.y;
-            B.y = -B.y;
-        }
-        x[e] = {A.x - B.y, A.y + B.x};  // A + iB
-    }
-    __syncthreads();  // twiddle table
-    fft_regs<R, PX, 1>(x, buf + pen * PS, tw, t);
+    inv_x_pair<R, PX>(W + ra * hx, W + rb * hx, va, vb, buf + pen * PS, tw, t, x);
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {  // nx <= Px/2
         const int xg = t + e * TPP;
@@ -84,7 +57,7 @@ __global__ __launch_bounds__((VolXCfg<R, PX>::NT)) void k_vol_x(const cx<R> *__r
 template <typename R, int KIND>
 struct VolumeLaunch {
     template <int P> static int x(const ApplyArgs &a, double *out, hipStream_t st) {
-        using Cfg = VolXCfg<R, P>;
+        using Cfg = RowInvCfg<R, P>;
         const int64_t nrows = (int64_t)Terms<KIND>::O * a.nzo * a.ny;
         const int64_t nb = (nrows + 2 * Cfg::PPB - 1) / (2 * Cfg::PPB);
         hipLaunchKernelGGL((k_vol_x<R, P>), dim3((unsigned)nb), dim3(Cfg::NT), 0, st,
