@@ -457,14 +457,18 @@ def test_batch_apply_matches_single_plans(dev, use_graph):
     batch.close()
 
 
-@pytest.mark.parametrize("kind", ["navier", "laplace2d"])
+@pytest.mark.parametrize("kind", ["navier", "laplace2d", "halfspace"])
 def test_batch_apply_other_kernels(dev, kind):
-    """Batches of Navier plans (3 components per node) and of 2D Laplace
-    plans: every member equals its own plan's apply bit for bit (graph
-    replayed twice), and one member matches the oracle."""
+    """Batches of Navier plans (3 components per node), of 2D Laplace plans
+    and of half-space plans: every member equals its own plan's apply bit for
+    bit (graph replayed twice), and one member matches the oracle."""
     if kind == "navier":
         geoms = [I.sphere3d(12, 0.35), I.sphere3d(16, 0.3), I.cube3d(12, 8)]
         kern, okern, nc, prec = B.NAVIER3D, O.NAVIER3D, 3, B.FP64
+    elif kind == "halfspace":
+        # two discs and a full 160^2 surface, whose long rows take the row FFT
+        geoms = [I.halfspace_patch(48, 0.3), I.halfspace_patch(32, 0.45), I.halfspace_patch(160)]
+        kern, okern, nc, prec = B.HALFSPACE, O.HALFSPACE, 3, B.FP64
     else:
         geoms = [I.circle2d(32, 0.4), I.circle2d(48, 0.3), I.square2d(40, 30)]
         kern, okern, nc, prec = B.LAPLACE2D, O.LAPLACE2D, 1, B.FP64
