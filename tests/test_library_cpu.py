@@ -80,6 +80,15 @@ def test_plan_validation_rejects_before_device_work(lib):
     # C_USER without values
     _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
                                          c_mode=B.C_USER), B.EINVAL)
+    # half-space: a 2D surface grid, elastic constants checked; normals are optional
+    hs = I.halfspace_patch(32, 0.3)
+    _expect(lambda: B.bemfft_plan_create(3, s.n, s.h, s.nodes, s.normals, s.weights, B.HALFSPACE), B.EINVAL)
+    _expect(lambda: B.bemfft_plan_create(2, hs.n, hs.h, hs.nodes, None, None, B.HALFSPACE, nu=0.5), B.EINVAL)
+    _expect(lambda: B.bemfft_plan_create(2, hs.n, hs.h, hs.nodes, None, None, B.HALFSPACE, mu=-1.0), B.EINVAL)
+    # unknown kernel family
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, 4), B.EINVAL)
+    # NULL normals are refused for the boundary families
+    _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, None, g.weights, B.LAPLACE2D), B.EINVAL)
 
 
 def test_null_arguments(lib):
