@@ -235,7 +235,7 @@ int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double 
  *      seconds; the other fields are 0 (x0_relres -1).
  * Returns 0, ENOCONV (maxit reached; q and info written), EBREAKDOWN (a
  * direction with p.Ap <= 0: the system is not positive definite, q is not
- * meaningful), EINVAL (Navier plan, null pointer, bad options), ENOMEM,
+ * meaningful), EINVAL (Navier or half-space plan, null pointer, bad options), ENOMEM,
  * EDEVICE.  Synchronises `stream`; not concurrent with other calls on the
  * same plan.
  */

@@ -646,7 +646,7 @@ extern "C" int bemfft_solve_cg(bemfft_plan *p, const double *u, double *q, const
         set_error("solve_cg: null argument");
         return BEMFFT_EINVAL;
     }
-    if (p->kernel == BEMFFT_NAVIER3D) {
+    if (p->kernel != BEMFFT_LAPLACE2D && p->kernel != BEMFFT_LAPLACE3D) {
         set_error("solve_cg: Laplace plans only");
         return BEMFFT_EINVAL;
     }

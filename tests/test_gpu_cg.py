@@ -93,6 +93,11 @@ def test_cg_rejects_navier_and_bad_options(dev):
     with pytest.raises(B.BemfftError):
         nav.solve_cg(u)
     nav.close()
+    hp = I.halfspace_patch(32, 0.3)
+    hs = B.Plan(hp, B.HALFSPACE)
+    with pytest.raises(B.BemfftError):
+        hs.solve_cg(torch.zeros(3 * hp.m, dtype=torch.float64, device=dev))
+    hs.close()
     lap = B.Plan(g, B.LAPLACE3D)
     u = torch.ones(g.m, dtype=torch.float64, device=dev)
     with pytest.raises(B.BemfftError):
