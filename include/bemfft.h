@@ -293,6 +293,8 @@ int bemfft_batch_destroy(bemfft_batch *b);
  * is 0 up to discretisation error.  At grid points that hold nodes it is
  * the plain grid sum (no free term, the grid's own value at offset 0 for
  * the single layer): use bemfft_apply for values on the boundary.
+ * For BEMFFT_HALFSPACE plans the box is the surface grid and out holds the
+ * surface displacement K[q] at every grid point (u is not used).
  *
  * q, u: device, [ncomp][m] as in bemfft_apply.  out: device, ncomp *
  * z_count * n[1] * n[0] doubles, x fastest.  Computed in the plan's working
