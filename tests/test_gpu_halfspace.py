@@ -68,12 +68,13 @@ def test_halfspace_full_size_sampled(dev, precision):
     assert info["pad"][0] == 512 and err < TOL[precision]
 
 
-def test_halfspace_grid_displacement(dev):
+@pytest.mark.parametrize("precision", [B.FP64, B.FP32])
+def test_halfspace_grid_displacement(dev, precision):
     # K[sigma] at every surface grid point, inside and outside the loaded disc
     g = I.halfspace_patch(64, 0.3)
     rng = np.random.default_rng(2)
     q = rng.uniform(-1, 1, (3, g.m))
-    plan = B.Plan(g, B.HALFSPACE, precision=B.FP64, nu=NU, mu=MU)
+    plan = B.Plan(g, B.HALFSPACE, precision=precision, nu=NU, mu=MU)
     out = plan.eval_grid(_t(q, dev), torch.zeros(3 * g.m, dtype=torch.float64, device=dev))
     got = out.cpu().numpy().reshape(3, -1)
     n = 64
@@ -82,7 +83,7 @@ def test_halfspace_grid_displacement(dev):
     idx = rng.choice(len(pts), 300, replace=False)
     p = O.problem(g, O.HALFSPACE, NU, MU)
     ref, sc = O.volume(p, q, np.zeros_like(q), pts[idx], with_scale=True)
-    assert np.abs(got[:, idx] + ref).max() / np.max(sc) < 1e-12
+    assert np.abs(got[:, idx] + ref).max() / np.max(sc) < TOL[precision]
     plan.close()
 
 
