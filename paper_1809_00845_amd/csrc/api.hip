@@ -24,6 +24,11 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 const int64_t kSizes[] = {32, 64, 96, 128, 192, 256, 320, 384, 512};
 // A grid row holding this many nodes is x-transformed by FFT.
 constexpr int kDenseRow = 24;
+// When no other row holds more than this many nodes, the forward direct DFT
+// takes two kx per thread (each node load serves both; measured on the
+// 128^3 cube: 42 -> 38 us).  Plans with busier short rows keep one kx per
+// thread, whose work per thread is then balanced better (the sphere).
+constexpr int kFewNodesRow = 4;
 // The long rows' inverse x transform goes through a row FFT (one more launch,
 // a few microseconds) when the per-node sums it replaces exceed this many
 // complex products: the nodes of long rows x Hx x outputs.  Measured: the
@@ -183,6 +188,7 @@ void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, Ap
     a.dense_rows = p->d_dense_rows;
     a.nd = (int)p->nd;
     a.row_inv = p->row_inv;
+    a.fwd_xg = p->fwd_xg;
     a.zsched = p->zsched;
     a.off = 0;
     a.gid = 0;
@@ -396,6 +402,14 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
         }
     }
     p->nd = (int64_t)dense_rows.size();
+    {
+        int64_t busiest = 0;  // nodes of the busiest row that is not a long row
+        for (size_t row = 0; row + 1 < rowptr.size(); ++row) {
+            const int64_t c = rowptr[row + 1] - rowptr[row];
+            if (c < kDenseRow) busiest = std::max(busiest, c);
+        }
+        p->fwd_xg = busiest <= kFewNodesRow ? 2 : 1;
+    }
     {
         int64_t long_nodes = 0;
         for (int r : dense_rows) long_nodes += rowptr[r + 1] - rowptr[r];

@@ -54,6 +54,7 @@ struct ApplyArgs {
     const int *dense_rows;  // [nd]: row index (zz * ny + y) of each long row
     int nd;
     int row_inv;            // 1: the long rows' inverse x transform is an FFT (k_rows_inv)
+    int fwd_xg;             // kx per thread in the forward direct DFT (1 or 2)
     void *Y, *Z;
 };
 
@@ -254,7 +255,9 @@ struct FwdCfg {
     static constexpr int NT = F * KXC * TPP;
 };
 
-template <typename R, int PY, int KIND>
+// XG: kx per thread in the direct DFT (1, or 2 on plans whose short rows
+// hold few nodes, where one node load then serves two kx).
+template <typename R, int PY, int KIND, int XG_>
 __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
     if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
     using Cfg = FwdCfg<R, PY, KIND>;
@@ -272,35 +275,54 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
     __syncthreads();
     const float inv_px = 1.0f / (float)a.px;
     // x-transform of the zero-extended fields for rows y < ny: a direct DFT
-    // over the row's few nodes, or the row FFT of a long row
-    for (int pr = tid; pr < KXC * a.ny; pr += NT) {
-        const int kxl = pr % KXC, y = pr / KXC, kx = kx0 + kxl;
-        if (kx >= a.hx) continue;
+    // over the row's few nodes, or the row FFT of a long row.  A thread takes
+    // one row and XG consecutive kx: each node's data is loaded once for the
+    // XG kx and its twiddles are stepped from (kx x) mod px.
+    constexpr int XG = clampi(XG_, 1, KXC);
+    constexpr int NG = (KXC + XG - 1) / XG;
+    for (int it = tid; it < NG * a.ny; it += NT) {
+        const int gk = it % NG, y = it / NG;
+        const int kxa = kx0 + gk * XG;
         const int row = zz * a.ny + y;
-        // the row's bounds and its long-row slot are independent loads: issue
-        // them together so the node loads wait on one round trip, not two
         const int dense = a.row_dense[row];
         const int r0 = a.rowptr[row], r1 = a.rowptr[row + 1];
-        cx<R> acc[F];
+        cx<R> acc[XG][F];
         if (dense >= 0) {
 #pragma unroll
-            for (int f = 0; f < F; ++f) acc[f] = Xd[((size_t)dense * F + f) * a.hx + kx];
+            for (int k = 0; k < XG; ++k)
+#pragma unroll
+                for (int f = 0; f < F; ++f)
+                    acc[k][f] = (kxa + k < a.hx) ? Xd[((size_t)dense * F + f) * a.hx + kxa + k] : cx<R>{R(0), R(0)};
         } else {
 #pragma unroll
-            for (int f = 0; f < F; ++f) acc[f] = {R(0), R(0)};
+            for (int k = 0; k < XG; ++k)
+#pragma unroll
+                for (int f = 0; f < F; ++f) acc[k][f] = {R(0), R(0)};
 #pragma unroll 4
             for (int s = r0; s < r1; ++s) {
-                const cx<R> w = gtwx[mod_small(kx, a.gx[s], a.px, inv_px)];  // through the caches
+                const int xg = a.gx[s];
+                R vv[F];
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    const R vv = vf[f * a.m + s];
-                    acc[f].x += vv * w.x;
-                    acc[f].y += vv * w.y;
+                for (int f = 0; f < F; ++f) vv[f] = vf[f * a.m + s];
+                int idx = mod_small(kxa, xg, a.px, inv_px);
+#pragma unroll
+                for (int k = 0; k < XG; ++k) {
+                    const cx<R> w = gtwx[idx];  // through the caches
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        acc[k][f].x += vv[f] * w.x;
+                        acc[k][f].y += vv[f] * w.y;
+                    }
+                    idx += xg;
+                    if (idx >= a.px) idx -= a.px;
                 }
             }
         }
 #pragma unroll
-        for (int f = 0; f < F; ++f) buf[(f * KXC + kxl) * PS + pslot(y)] = acc[f];
+        for (int k = 0; k < XG; ++k)
+            if (gk * XG + k < KXC)
+#pragma unroll
+                for (int f = 0; f < F; ++f) buf[(f * KXC + gk * XG + k) * PS + pslot(y)] = acc[k][f];
     }
     __syncthreads();
     // y-FFT in registers (rows y >= ny are zero), stored straight from them
@@ -322,9 +344,9 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
     }
 }
 
-template <typename R, int PY, int KIND>
+template <typename R, int PY, int KIND, int XG>
 __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
-    fwd_xy_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+    fwd_xy_body<R, PY, KIND, XG>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -335,7 +357,7 @@ __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void kb_fwd_xy(const App
     a.q = io->q + a.off;
     a.u = io->u + a.off;
     a.r = io->r + a.off;
-    fwd_xy_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
+    fwd_xy_body<R, PY, KIND, 1>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
 }
 
 // ------------------------------------------------------------------ k_zpass
@@ -811,7 +833,8 @@ template <typename R, int PY, int KIND>
 int launch_fwd(const ApplyArgs &a, hipStream_t st) {
     using Cfg = FwdCfg<R, PY, KIND>;
     dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
-    hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a);
+    if (a.fwd_xg == 2) hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 2>), grid, dim3(Cfg::NT), 0, st, a);
+    else hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 1>), grid, dim3(Cfg::NT), 0, st, a);
     BF_HIP(hipGetLastError());
     return 0;
 }

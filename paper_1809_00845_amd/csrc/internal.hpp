@@ -78,6 +78,7 @@ struct bemfft_plan {
     int *d_dense_rows = nullptr;  // [nd]
     int64_t nd = 0;               // rows whose x-transform is an FFT
     int row_inv = 0;              // their inverse x transform is an FFT too
+    int fwd_xg = 1;               // kx per thread in the forward direct DFT
     double h = 0.0, nu = 0.0, mu = 0.0;
     double origin[3] = {0, 0, 0};
     // node arrays in sorted order (z, y, x)
