@@ -20,8 +20,9 @@
  *     S[q]_j = sum_k G(p_k - p_j) w_k q_k,   D[u]_j = sum_k H(p_k - p_j; n_k) w_k u_k
  *   G: single-layer kernel (u* of eq. 3 in 2D, 1/(4 pi r) in 3D, Kelvin's
  *   tensor of eq. 7); H: double-layer kernel (q* of eq. 12 / its 3D analogue,
- *   Kelvin's traction kernel).  w_k: boundary measure of node k (the "divide
- *   by the discretisation length" of Sec. 4 folded into a weight).  Pairs in
+ *   Kelvin's traction kernel).  w_k: boundary measure of node k (Sec. 4
+ *   scales the grid sums by the discretisation length; here that factor is
+ *   folded into a per-node weight).  Pairs in
  *   one grid cell: single layer uses the grid value at offset 0 (flat-panel
  *   integral over h^(d-1), divided by it; Navier: orientation average), the
  *   node itself uses the flat-panel integral over its own w_j; double layer 0.
@@ -92,8 +93,8 @@ typedef enum { BEMFFT_C_HALF = 0, BEMFFT_C_USER = 1, BEMFFT_C_IMPLICIT = 2 } bem
 
 /* Uniform grid: n[a] points per axis at origin + h * g, g in [0, n[a]).
  * dim = 2 uses n[0], n[1] (n[2] ignored).  pad[a] = padded FFT length per
- * axis; 0 picks the smallest supported even length >= 2 n[a] ("extended in
- * the appropriate fashion", Sec. 4). */
+ * axis; 0 picks the smallest supported even length >= 2 n[a] (Sec. 4 pads the
+ * space for the FFT without fixing the size). */
 typedef struct {
     int dim;
     int64_t n[3];

@@ -7,14 +7,22 @@ and never imports it.
 The arithmetic lives in ``bem_oracle.c`` (plain C, FP64, OpenMP over targets):
 a direct O(M^2) summation of the discrete operator that the FFT convolution of
 the paper (Sec. 3, eqs. 14-16) evaluates.  This module only marshals arrays and
-adds two textbook steps on top: a dense LU solve of the assembled system
-(``numpy.linalg.solve``) and a plain restarted GMRES written from its
-definition, for the mixed boundary-value problem of eq. (4)/(8).
+adds textbook steps on top, for the mixed boundary-value problem of eq. (4)/(8)
+and the paper's Dirichlet problem (end of Sec. 4):
+
+* a dense LU solve of the assembled system (``numpy.linalg.solve``), for
+  problems whose dense matrix fits (``solve_lu``);
+* a plain restarted GMRES written from its definition (Saad and Schultz,
+  1986: Arnoldi with modified Gram-Schmidt, Givens rotations, restart), with
+  the direct-sum operator applied matrix-free, for problems beyond LU sizes
+  (``gmres``, ``solve_gmres``);
+* conjugate gradients on the symmetrised Dirichlet system (``dirichlet_cg``).
 """
 
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -344,3 +352,132 @@ def dirichlet_cg(p: Problem, u, tol=1e-10, maxit=1000, precond=True, cmode=C_IMP
         rz = rz_new
         it += 1
     return y / sw, it
+
+
+# ----------------------------------------------------------------- GMRES
+
+
+def gmres(matvec, b, tol=1e-10, restart=50, maxit=1000, minv=None, x0=None):
+    """Restarted GMRES(restart) for A x = b, written from its definition.
+
+    Right preconditioning by the diagonal ``minv`` (A M y = b, x = M y).  Each
+    cycle starts from the true residual r0 = b - A x; the Arnoldi process with
+    modified Gram-Schmidt builds V and the Hessenberg matrix H, Givens
+    rotations reduce H to triangular form, and the residual norm of the
+    least-squares problem min ||beta e1 - H y|| is the last rotated entry of
+    beta e1.  A cycle ends at ``restart`` steps or when that norm falls to
+    tol ||b||; x += M V y.  Stops when the true residual ||b - A x|| <= tol
+    ||b|| or after ``maxit`` iterations.
+
+    Returns (x, iterations, true relative residual, per-iteration estimated
+    relative residuals)."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    M = np.ones(n) if minv is None else np.asarray(minv, dtype=np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    bnorm = np.linalg.norm(b)
+    history = []
+    if bnorm == 0.0:
+        return np.zeros(n), 0, 0.0, history
+    iters = 0
+    while True:
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+        if beta <= tol * bnorm or iters >= maxit:
+            return x, iters, beta / bnorm, history
+        m = min(restart, maxit - iters)
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        while k < m:
+            w = matvec(M * V[k])
+            for i in range(k + 1):  # modified Gram-Schmidt
+                H[i, k] = V[i] @ w
+                w = w - H[i, k] * V[i]
+            H[k + 1, k] = np.linalg.norm(w)
+            for i in range(k):  # earlier rotations on the new column
+                t = cs[i] * H[i, k] + sn[i] * H[i + 1, k]
+                H[i + 1, k] = -sn[i] * H[i, k] + cs[i] * H[i + 1, k]
+                H[i, k] = t
+            rr = math.hypot(H[k, k], H[k + 1, k])
+            cs[k], sn[k] = (H[k, k] / rr, H[k + 1, k] / rr) if rr > 0 else (1.0, 0.0)
+            hnext = H[k + 1, k]
+            H[k, k], H[k + 1, k] = rr, 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            iters += 1
+            k += 1
+            history.append(abs(g[k]) / bnorm)
+            if abs(g[k]) <= tol * bnorm or hnext == 0.0:
+                break
+            V[k] = w / hnext
+        y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
+        x = x + M * (V[:k].T @ y)
+
+
+def mixed_parts(p: Problem, bc, known):
+    """(q, u) of the known values placed in their slots, and a function that
+    places an unknown vector x in the other slots (bc == 0: u known, q
+    unknown; bc == 1: q known, u unknown)."""
+    nc, m = p.ncomp, p.m
+    bc = np.reshape(bc, (nc, m)).astype(bool)
+    known = np.reshape(known, (nc, m))
+    qk = np.where(bc, known, 0.0)
+    uk = np.where(bc, 0.0, known)
+
+    def place(x):
+        x = np.reshape(x, (nc, m))
+        return np.where(bc, 0.0, x), np.where(bc, x, 0.0)
+
+    return qk, uk, place
+
+
+def mixed_diagonal(p: Problem, bc, cmode=C_IMPLICIT, cuser=None):
+    """Diagonal of the mixed operator: -S_jj (the node's flat-panel self
+    integral) where q is unknown, c_jj + D_jj = c_jj where u is unknown
+    (the double-layer self term is zero)."""
+    nc, m = p.ncomp, p.m
+    bc = np.reshape(bc, (nc, m)).astype(bool)
+    _, cblk = apply(p, np.zeros((nc, m)), np.zeros((nc, m)), cmode=cmode, cuser=cuser, with_c=True)
+    cblk = np.reshape(cblk, (m, nc, nc))
+    sdiag = np.zeros((nc, m))
+    for j in range(m):
+        w = p.weights[j]
+        if p.kernel == LAPLACE2D:
+            sdiag[0, j] = self_laplace2d(w)
+        elif p.kernel == LAPLACE3D:
+            sdiag[0, j] = self_laplace3d(w)
+        elif p.kernel == NAVIER3D:
+            sdiag[:, j] = np.diag(self_kelvin(w, p.normals[j], p.nu, p.mu))
+        else:
+            raise ValueError("mixed_diagonal: boundary families only")
+    cdiag = np.stack([cblk[:, k, k] for k in range(nc)])
+    return np.where(bc, cdiag, -sdiag).reshape(-1)
+
+
+def solve_gmres(p: Problem, bc, known, tol=1e-10, restart=50, maxit=2000, precond=True, cmode=C_IMPLICIT,
+                cuser=None):
+    """The mixed problem A x = b with A x = apply(x in the unknown slots) and
+    b = -apply(known values), by ``gmres`` with the direct-sum operator
+    applied matrix-free (each product is one O(M^2) ``apply``).  Jacobi
+    (right) scaling with ``mixed_diagonal`` if precond.  Returns (x,
+    iterations, true relative residual), x shaped like ``known``."""
+    nc, m = p.ncomp, p.m
+    qk, uk, place = mixed_parts(p, bc, known)
+    b = -np.reshape(apply(p, qk, uk, cmode=cmode, cuser=cuser), -1)
+
+    def matvec(x):
+        q, u = place(x)
+        return np.reshape(apply(p, q, u, cmode=cmode, cuser=cuser), -1)
+
+    minv = None
+    if precond:
+        d = mixed_diagonal(p, bc, cmode, cuser)
+        minv = np.where((d != 0) & np.isfinite(d), 1.0 / np.where(d != 0, d, 1.0), 1.0)
+    x, it, rel, _ = gmres(matvec, b, tol=tol, restart=restart, maxit=maxit, minv=minv)
+    return (x.reshape(nc, m) if nc > 1 else x), it, rel

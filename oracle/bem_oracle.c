@@ -21,8 +21,9 @@
  *     r_j    = c_j u_j + D[u]_j - S[q]_j           (residual of eq. 4 / 8)
  *
  *   with p_j = origin + h g_j the node's grid point, g_j = floor((x_j -
- *   origin)/h + 1/2), w_k the boundary measure carried by node k (the
- *   "divide by the discretisation length" of Sec. 4 folded into the weight),
+ *   origin)/h + 1/2), w_k the boundary measure carried by node k (Sec. 4
+ *   scales the grid sums by the discretisation length; that factor is folded
+ *   into the weight),
  *   and n_k the node's mean outward normal.
  *
  * Readings of points the paper leaves open (each one is listed with its

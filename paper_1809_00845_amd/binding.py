@@ -140,11 +140,44 @@ def _check(status, where):
     return status
 
 
-def _ptr(t):
-    """Device pointer of a torch tensor (must be contiguous)."""
+def _ptr(t, n=None, dtype=None, name="tensor"):
+    """Device pointer of a torch tensor.  The tensor must be a contiguous
+    GPU tensor; with ``dtype`` it must have that torch dtype, with ``n``
+    exactly n elements.  Checked here, before any library call, because the
+    library trusts the sizes it is given."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t, n, name):
+    import torch
+
+    return _ptr(t, n, torch.float64, name)
+
+
+def _u8(t, n, name):
+    import torch
+
+    return _ptr(t, n, torch.uint8, name)
+
+
+def _plan_len(plan, n):
+    """ncomp * m of a plan handle (looked up when the caller did not say)."""
+    if n is not None:
+        return int(n)
+    inf = bemfft_plan_get_info(plan)
+    return int(inf["ncomp"]) * int(inf["m"])
 
 
 def _stream_ptr(stream):
@@ -200,39 +233,49 @@ def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.
     return h_
 
 
-def bemfft_apply(plan, q, u, r, stream=None):
-    return _check(load().bemfft_apply(plan, _ptr(q), _ptr(u), _ptr(r), _stream_ptr(stream)), "bemfft_apply")
+def bemfft_apply(plan, q, u, r, stream=None, n=None):
+    """n: ncomp * m of the plan (looked up if None)."""
+    n = _plan_len(plan, n)
+    return _check(load().bemfft_apply(plan, _f64(q, n, "q"), _f64(u, n, "u"), _f64(r, n, "r"),
+                                      _stream_ptr(stream)), "bemfft_apply")
 
 
-def bemfft_eval_grid(plan, q, u, out, stream=None):
-    return _check(load().bemfft_eval_grid(plan, _ptr(q), _ptr(u), _ptr(out), _stream_ptr(stream)),
-                  "bemfft_eval_grid")
+def bemfft_eval_grid(plan, q, u, out, stream=None, n=None):
+    inf = bemfft_plan_get_info(plan)
+    n = _plan_len(plan, n)
+    nout = int(inf["ncomp"]) * int(inf["z_count"]) * int(inf["n"][1]) * int(inf["n"][0])
+    return _check(load().bemfft_eval_grid(plan, _f64(q, n, "q"), _f64(u, n, "u"), _f64(out, nout, "out"),
+                                          _stream_ptr(stream)), "bemfft_eval_grid")
 
 
-def bemfft_apply_profile(plan, q, u, r, reps=10, stream=None):
+def bemfft_apply_profile(plan, q, u, r, reps=10, stream=None, n=None):
     """Mean per-stage milliseconds (fwd_xy, zpass, inv_y, gather)."""
+    n = _plan_len(plan, n)
     ms = (ctypes.c_double * 4)()
-    _check(load().bemfft_apply_profile(plan, _ptr(q), _ptr(u), _ptr(r), int(reps), ms, _stream_ptr(stream)),
-           "bemfft_apply_profile")
+    _check(load().bemfft_apply_profile(plan, _f64(q, n, "q"), _f64(u, n, "u"), _f64(r, n, "r"), int(reps), ms,
+                                       _stream_ptr(stream)), "bemfft_apply_profile")
     return [float(v) for v in ms]
 
 
 def bemfft_solve(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, precond=1, use_x0=0,
-                 refine=0, inner_tol=1e-4, max_outer=20, stream=None):
+                 refine=0, inner_tol=1e-4, max_outer=20, stream=None, n=None):
+    n = _plan_len(plan, n)
     o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0, refine, inner_tol, max_outer)
     info = bemfft_solve_info()
-    st = load().bemfft_solve(plan, _ptr(bc), _ptr(known), _ptr(unknown), ctypes.byref(o), ctypes.byref(info),
-                             _stream_ptr(stream))
+    st = load().bemfft_solve(plan, _u8(bc, n, "bc"), _f64(known, n, "known"), _f64(unknown, n, "unknown"),
+                             ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
     _check(st, "bemfft_solve")
     return {"status": st, "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
             "seconds": info.seconds, "outer": info.outer, "applies64": info.applies64,
             "x0_used": info.x0_used, "x0_relres": info.x0_relres}
 
 
-def bemfft_solve_cg(plan, u, q, tol=1e-6, maxit=1000, precond=1, use_x0=0, stream=None):
+def bemfft_solve_cg(plan, u, q, tol=1e-6, maxit=1000, precond=1, use_x0=0, stream=None, n=None):
+    n = _plan_len(plan, n)
     o = bemfft_solve_opts(tol, 100, maxit, precond, use_x0, 0, 1e-4, 20)
     info = bemfft_solve_info()
-    st = load().bemfft_solve_cg(plan, _ptr(u), _ptr(q), ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+    st = load().bemfft_solve_cg(plan, _f64(u, n, "u"), _f64(q, n, "q"), ctypes.byref(o), ctypes.byref(info),
+                                _stream_ptr(stream))
     _check(st, "bemfft_solve_cg")
     return {"status": st, "iters": info.iters, "true_relres": info.true_relres, "seconds": info.seconds}
 
@@ -260,7 +303,10 @@ def bemfft_plan_destroy(plan):
 
 
 def bemfft_fft3d_c2c_f64(data, px, py, pz, direction, stream=None):
-    return _check(load().bemfft_fft3d_c2c_f64(_ptr(data), px, py, pz, direction, _stream_ptr(stream)),
+    import torch
+
+    return _check(load().bemfft_fft3d_c2c_f64(_ptr(data, 2 * px * py * pz, torch.float64, "data"), px, py, pz,
+                                              direction, _stream_ptr(stream)),
                   "bemfft_fft3d_c2c_f64")
 
 
@@ -283,7 +329,7 @@ class Plan:
 
         if r is None:
             r = torch.empty_like(u)
-        bemfft_apply(self.handle, q, u, r, stream)
+        bemfft_apply(self.handle, q, u, r, stream, n=self.ncomp * self.m)
         return r
 
     def eval_grid(self, q, u, out=None, stream=None):
@@ -297,7 +343,7 @@ class Plan:
             out = torch.empty(shape, dtype=torch.float64, device=u.device)
         elif out.dtype != torch.float64 or out.numel() != int(np.prod(shape)):
             raise ValueError(f"eval_grid: out needs {shape} float64 values")
-        bemfft_eval_grid(self.handle, q, u, out, stream)
+        bemfft_eval_grid(self.handle, q, u, out, stream, n=self.ncomp * self.m)
         if inf["dim"] == 2:
             return out[:, 0] if self.ncomp > 1 else out[0, 0]
         return out
@@ -308,7 +354,7 @@ class Plan:
         if unknown is None:
             unknown = torch.zeros_like(known, memory_format=torch.contiguous_format)
             kw.setdefault("use_x0", 0)
-        info = bemfft_solve(self.handle, bc, known, unknown, **kw)
+        info = bemfft_solve(self.handle, bc, known, unknown, n=self.ncomp * self.m, **kw)
         return unknown, info
 
     def solve_cg(self, u, q=None, **kw):
@@ -319,7 +365,7 @@ class Plan:
         if q is None:
             q = torch.zeros_like(u, memory_format=torch.contiguous_format)
             kw.setdefault("use_x0", 0)
-        info = bemfft_solve_cg(self.handle, u, q, **kw)
+        info = bemfft_solve_cg(self.handle, u, q, n=self.ncomp * self.m, **kw)
         return q, info
 
     def info(self):
@@ -360,15 +406,17 @@ class Batch:
         self.nrhs = nrhs
 
     def apply(self, q, u, r, stream=None):
-        return _check(load().bemfft_batch_apply(self.handle, _ptr(q), _ptr(u), _ptr(r), _stream_ptr(stream)),
-                      "bemfft_batch_apply")
+        n = self.total
+        return _check(load().bemfft_batch_apply(self.handle, _f64(q, n, "q"), _f64(u, n, "u"), _f64(r, n, "r"),
+                                                _stream_ptr(stream)), "bemfft_batch_apply")
 
     def solve(self, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, precond=1, use_x0=0, stream=None):
         nm = len(self.offsets)
         o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0, 0, 1e-4, 20)
         info = (bemfft_solve_info * nm)()
-        st = load().bemfft_batch_solve(self.handle, _ptr(bc), _ptr(known), _ptr(unknown), ctypes.byref(o), info,
-                                       _stream_ptr(stream))
+        n = self.total
+        st = load().bemfft_batch_solve(self.handle, _u8(bc, n, "bc"), _f64(known, n, "known"),
+                                       _f64(unknown, n, "unknown"), ctypes.byref(o), info, _stream_ptr(stream))
         _check(st, "bemfft_batch_solve")
         return st, [{"iters": i.iters, "true_relres": i.true_relres, "status": i.status, "seconds": i.seconds}
                     for i in info]
@@ -409,6 +457,17 @@ class Net:
         self.nparam = int(load().bemfft_net_num_params(self.handle))
         self.V = self.grid ** 3
 
+    def _targets(self, x, vox, tgt, wt):
+        """Check the training arguments; returns the target count."""
+        import torch
+
+        nt = int(vox.numel())
+        _ptr(x, 6 * self.V, torch.float32, "x")
+        _ptr(vox, nt, torch.int32, "vox")
+        _ptr(tgt, nt, torch.float32, "tgt")
+        _ptr(wt, nt, torch.float32, "wt")
+        return nt
+
     def params(self):
         buf = np.zeros(self.nparam, dtype=np.float32)
         _check(load().bemfft_net_get_params(self.handle, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
@@ -423,36 +482,55 @@ class Net:
                "bemfft_net_set_params")
 
     def input(self, plan, bc, known, scale, x, stream=None):
-        _check(load().bemfft_net_input(self.handle, plan.handle, _ptr(bc) if bc is not None else None, _ptr(known),
-                                       float(scale), _ptr(x), _stream_ptr(stream)), "bemfft_net_input")
+        import torch
+
+        n = plan.ncomp * plan.m
+        _check(load().bemfft_net_input(self.handle, plan.handle, _u8(bc, n, "bc") if bc is not None else None,
+                                       _f64(known, n, "known"), float(scale),
+                                       _ptr(x, 6 * self.V, torch.float32, "x"), _stream_ptr(stream)),
+               "bemfft_net_input")
         return x
 
     def forward(self, x, y, stream=None):
-        _check(load().bemfft_net_forward(self.handle, _ptr(x), _ptr(y), _stream_ptr(stream)), "bemfft_net_forward")
+        import torch
+
+        _check(load().bemfft_net_forward(self.handle, _ptr(x, 6 * self.V, torch.float32, "x"),
+                                         _ptr(y, self.V, torch.float32, "y"), _stream_ptr(stream)),
+               "bemfft_net_forward")
         return y
 
     def infer(self, x, y, stream=None):
-        _check(load().bemfft_net_infer(self.handle, _ptr(x), _ptr(y), _stream_ptr(stream)), "bemfft_net_infer")
+        import torch
+
+        _check(load().bemfft_net_infer(self.handle, _ptr(x, 6 * self.V, torch.float32, "x"),
+                                       _ptr(y, self.V, torch.float32, "y"), _stream_ptr(stream)),
+               "bemfft_net_infer")
         return y
 
     def gradients(self, x, vox, tgt, wt, stream=None):
         loss = ctypes.c_double()
         g = np.zeros(self.nparam, dtype=np.float32)
-        _check(load().bemfft_net_gradients(self.handle, _ptr(x), int(vox.numel()), _ptr(vox), _ptr(tgt), _ptr(wt),
+        nt = self._targets(x, vox, tgt, wt)
+        _check(load().bemfft_net_gradients(self.handle, _ptr(x), nt, _ptr(vox), _ptr(tgt), _ptr(wt),
                                            ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                            _stream_ptr(stream)), "bemfft_net_gradients")
         return loss.value, g
 
     def train_step(self, x, vox, tgt, wt, lr, stream=None):
         loss = ctypes.c_double()
-        _check(load().bemfft_net_train_step(self.handle, _ptr(x), int(vox.numel()), _ptr(vox), _ptr(tgt), _ptr(wt),
+        nt = self._targets(x, vox, tgt, wt)
+        _check(load().bemfft_net_train_step(self.handle, _ptr(x), nt, _ptr(vox), _ptr(tgt), _ptr(wt),
                                             float(lr), ctypes.byref(loss), _stream_ptr(stream)),
                "bemfft_net_train_step")
         return loss.value
 
     def guess(self, plan, bc, known, xbuf, x0, stream=None):
-        _check(load().bemfft_net_guess(self.handle, plan.handle, _ptr(bc) if bc is not None else None, _ptr(known),
-                                       _ptr(xbuf), _ptr(x0), _stream_ptr(stream)), "bemfft_net_guess")
+        import torch
+
+        n = plan.ncomp * plan.m
+        _check(load().bemfft_net_guess(self.handle, plan.handle, _u8(bc, n, "bc") if bc is not None else None,
+                                       _f64(known, n, "known"), _ptr(xbuf, 6 * self.V, torch.float32, "xbuf"),
+                                       _f64(x0, n, "x0"), _stream_ptr(stream)), "bemfft_net_guess")
         return x0
 
     def close(self):

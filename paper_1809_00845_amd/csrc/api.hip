@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -301,7 +302,13 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     const bool halfspace = kernel == BEMFFT_HALFSPACE;
     KindInfo ki = kind_info(kernel);
     if (grid->dim != ki.dim) { set_error("grid dimension does not match the kernel"); return BEMFFT_EINVAL; }
-    if (m < 1 || m > (int64_t)1 << 30) { set_error("node count out of range"); return BEMFFT_EINVAL; }
+    // kernels index the [F][m] field and [O][m] node arrays with 32-bit products
+    // (f * m + s, with F up to 9), and the plan sorts with 32-bit node indices
+    const int64_t m_max = (int64_t)INT32_MAX / std::max(ki.F, 3);
+    if (m < 1 || m > m_max) {
+        set_error("node count out of range [1, " + std::to_string(m_max) + "]");
+        return BEMFFT_EINVAL;
+    }
     if (!nodes || (!normals && !halfspace)) { set_error("nodes and normals are required"); return BEMFFT_EINVAL; }
     if (!(grid->h > 0.0) || !std::isfinite(grid->h)) { set_error("grid spacing must be positive"); return BEMFFT_EINVAL; }
     if ((kernel == BEMFFT_NAVIER3D || halfspace) && (!(nu > -1.0 && nu < 0.5) || !(mu > 0.0))) {

@@ -13,8 +13,8 @@
 //              registers/LDS, rows y < ny stored with kx contiguous
 //                                                      -> W[o][z][y][kx] (in Y)
 //   k_gather   eight lanes per node: the inverse x-transform of its row
-//              evaluated only at its own x ("the values of interest lie only
-//              on the boundary", Sec. 4), plus c u and the self-term
+//              evaluated only at its own x (Sec. 4: only the boundary
+//              values are needed), plus c u and the self-term
 //              correction                              -> r
 //              (nodes of long rows read their row's inverse FFT, made by
 //              k_rows_inv, instead)

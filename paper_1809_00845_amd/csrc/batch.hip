@@ -57,6 +57,7 @@ struct bemfft_batch {
     double *s_V = nullptr, *s_vec = nullptr, *s_red = nullptr, *s_hb = nullptr, *s_hc = nullptr;
     double *h_hc = nullptr;           // pinned copy of the compact Hessenberg columns
     int64_t *d_off = nullptr, *d_len = nullptr, *d_voff = nullptr;
+    int *d_kc = nullptr;              // basis columns used by each member's update
     int *h_active = nullptr;          // pinned
 };
 
@@ -170,10 +171,14 @@ __global__ __launch_bounds__(64) void kbs_mdot_final(const double *partial, int 
 }
 
 // w_k += sign * V_k h_k, h_k = hb[k * kHs + base ...]
+// kcount (optional): member k uses only its first kcount[k] <= nvec columns
+// (a member that stopped early has no coefficients, and possibly never-written
+// basis columns, beyond them).
 __global__ void kbs_gemv(const double *V, const int64_t *voff, const int64_t *off, const int64_t *len, int nvec,
-                         const double *hb, int base, double *w, double sign, const int *active) {
+                         const double *hb, int base, double *w, double sign, const int *active, const int *kcount) {
     const int k = blockIdx.y;
     if (!active[k]) return;
+    if (kcount) nvec = min(nvec, kcount[k]);
     const int64_t n = len[k];
     const double *Vk = V + voff[k];
     const double *h = hb + (int64_t)k * kHs + base;
@@ -246,6 +251,8 @@ int ensure_solve_ws(bemfft_batch *b, int restart) {
             set_error("batched GMRES basis allocation failed");
             return BEMFFT_ENOMEM;
         }
+        // columns a member never reaches stay finite (zero) whatever the memory held
+        BF_HIP(hipMemset(b->s_V, 0, (size_t)(restart + 1) * b->total * sizeof(double)));
         b->s_cap = restart + 1;
         std::vector<int64_t> voff(nm);
         for (int k = 0; k < nm; ++k) voff[k] = (int64_t)(restart + 1) * b->mem_off[k];
@@ -259,6 +266,7 @@ int ensure_solve_ws(bemfft_batch *b, int restart) {
             hipMalloc(&b->s_red, (size_t)nm * kBpm * 512 * sizeof(double)) != hipSuccess ||
             hipMalloc(&b->s_hb, (size_t)nm * kHs * sizeof(double)) != hipSuccess ||
             hipMalloc(&b->s_hc, (size_t)nm * 512 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&b->d_kc, (size_t)nm * sizeof(int)) != hipSuccess ||
             hipHostMalloc(&b->h_hc, (size_t)nm * 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
             set_error("batched GMRES workspace allocation failed");
             return BEMFFT_ENOMEM;
@@ -292,6 +300,7 @@ int bemfft_batch_destroy(bemfft_batch *b) {
     bfree(b->d_off);
     bfree(b->d_len);
     bfree(b->d_voff);
+    bfree(b->d_kc);
     delete b;
     return 0;
 }
@@ -504,8 +513,14 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
     std::vector<double> H((size_t)nm * (mcap + 1) * mcap), cs((size_t)nm * mcap), sn((size_t)nm * mcap),
         g((size_t)nm * (mcap + 1));
     bool x_zero = !o.use_x0;
-    for (int k = 0; k < nm; ++k)
-        if (!(bnorm[k] > 0.0)) conv[k] = 1;  // zero data: x = 0
+    for (int k = 0; k < nm; ++k) {
+        if (!std::isfinite(bnorm[k])) {  // non-finite data: breakdown, not "zero data"
+            status_m[k] = BEMFFT_EBREAKDOWN;
+            conv[k] = 1;
+        } else if (!(bnorm[k] > 0.0)) {
+            conv[k] = 1;  // zero data: x = 0
+        }
+    }
     for (;;) {
         // true residuals of the members not yet converged
         for (int k = 0; k < nm; ++k) act[k] = conv[k] ? 0 : 1;
@@ -564,7 +579,7 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
                 hipLaunchKernelGGL(kbs_mdot_final, dim3(nm, it + 1), dim3(64), 0, st, b->s_red, kBpm, it + 1, b->s_hb, base, 0,
                                    b->d_active);
                 hipLaunchKernelGGL(kbs_gemv, gm, dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len, it + 1, b->s_hb,
-                                   base, w, -1.0, b->d_active);
+                                   base, w, -1.0, b->d_active, (const int *)nullptr);
             }
             hipLaunchKernelGGL(kbs_mdot_partial, dim3(kBpm, nm), dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len, 1,
                                w, b->s_red, b->d_active, 1);
@@ -632,9 +647,10 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
         }
         BF_CHECK(upload_active());
         BF_HIP(hipMemcpyAsync(b->s_hb, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        BF_HIP(hipMemcpyAsync(b->d_kc, kk.data(), nm * sizeof(int), hipMemcpyHostToDevice, st));
         BF_HIP(hipMemsetAsync(r, 0, n * sizeof(double), st));
         hipLaunchKernelGGL(kbs_gemv, gm, dim3(256), 0, st, V, b->d_voff, b->d_off, b->d_len, maxk, b->s_hb, 0, r, 1.0,
-                           b->d_active);
+                           b->d_active, (const int *)b->d_kc);
         hipLaunchKernelGGL(kbs_axpy_scaled, dim3(gridn(n)), dim3(256), 0, st, x, dinv, r, n);
         BF_HIP(hipGetLastError());
         x_zero = false;

@@ -1,8 +1,8 @@
 // solve.hip -- restarted GMRES for the mixed boundary-value problem.
 //
-// The paper obtains the unknown q "with a conjugate gradient method" in which
-// the first integral is evaluated by the FFT like the others, iterating until
-// the residual norm falls below a preset value (end of Sec. 4).  The operator
+// At the end of Sec. 4 the paper finds the unknown q by conjugate gradients,
+// with the first integral also evaluated through the FFT, and stops once the
+// residual norm is below a chosen bound.  The operator
 // of a mixed problem is not symmetric, so the iteration used here is GMRES
 // with right Jacobi scaling; every matrix-vector product is one apply.
 // Arnoldi uses classical Gram-Schmidt applied twice (two block reductions

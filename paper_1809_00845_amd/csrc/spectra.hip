@@ -1,8 +1,8 @@
 // spectra.hip -- kernel sampling on the padded grid and its FP64 transform.
 //
-// "The three kernel functions ... are roughly approximated on constant
-// elements on the entire parameter space which is extended for the
-// application of the FFT" (Sec. 4, Fig. 5).  Reading used here: the kernel
+// Sec. 4 (Fig. 5) discretises the kernel functions coarsely, as constant
+// values per element, over the whole zero-padded space that the FFT acts
+// on.  Reading used here: the kernel
 // is point-sampled at every padded-grid offset m (m_a in [-P_a/2, P_a/2)),
 // with the flat-panel value at m = 0 for the single layer (0 for the odd
 // double-layer kernels) and 0 on the planes m_a = -P_a/2, which no pair of

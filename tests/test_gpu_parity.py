@@ -179,6 +179,37 @@ def test_single_node_and_duplicates(dev):
     assert err < 1e-12
 
 
+def test_navier_nodes_sharing_cells(dev):
+    """Navier nodes in pairs and triples per cell (different normals and
+    weights): the same-cell single layer uses the orientation-averaged grid
+    value, each node its own panel block, the double layer 0 between them."""
+    base = I.sphere3d(16, 0.35)
+    rng = np.random.default_rng(21)
+    pick = rng.choice(base.m, 40, replace=False)
+    extra_nodes = base.nodes[pick] + rng.uniform(-0.3, 0.3, (40, 3)) * base.h
+    # stay inside the original node's cell
+    gi = np.floor(base.nodes[pick] / base.h + 0.5)
+    extra_nodes = np.clip(extra_nodes, (gi - 0.49) * base.h, (gi + 0.49) * base.h)
+    nv = base.normals[pick] + 0.5 * rng.normal(size=(40, 3))
+    nv /= np.linalg.norm(nv, axis=1, keepdims=True)
+
+    class G:
+        pass
+
+    g = G()
+    g.dim, g.n, g.h, g.origin = 3, base.n, base.h, base.origin
+    g.nodes = np.concatenate([base.nodes, extra_nodes, extra_nodes[:10] + 0.1 * base.h])
+    g.normals = np.concatenate([base.normals, nv, nv[:10]])
+    g.weights = np.concatenate([base.weights, rng.uniform(0.2, 1.2, 40) * base.h ** 2,
+                                rng.uniform(0.2, 1.2, 10) * base.h ** 2])
+    gg = np.floor(g.nodes / g.h + 0.5).astype(int)
+    assert len({tuple(v) for v in gg}) == base.m  # every extra node shares a cell
+    for cmode in (B.C_IMPLICIT, B.C_HALF):
+        for prec in (B.FP64, B.FP32):
+            err, _ = _parity(dev, g, B.NAVIER3D, prec, cmode, nu=0.3, mu=1.0)
+            assert err < TOL[prec], (cmode, prec, err)
+
+
 # ------------------------------------------------------------------ Navier
 
 
@@ -212,10 +243,16 @@ def test_config2_sphere_full_size_sampled(dev):
 
 
 def test_config2_cube_full_size_sampled(dev):
+    """Cube of 100 points per edge on 128^3 (58,808 nodes), padded 256^3, in
+    FP32 and FP64; two target samples: the first face's rows and a run of
+    edge and corner nodes further on."""
     g = I.cube3d(128, 100)
     assert g.m == 58808
-    err, _ = _parity(dev, g, B.LAPLACE3D, B.FP32, targets=(0, 400))
-    assert err < TOL[B.FP32]
+    for prec in (B.FP32, B.FP64):
+        for targets in ((0, 400), (29000, 29400)):
+            err, info = _parity(dev, g, B.LAPLACE3D, prec, targets=targets)
+            assert info["pad"] == [256, 256, 256]
+            assert err < TOL[prec], (prec, targets, err)
 
 
 @pytest.fixture(scope="module")

@@ -104,3 +104,50 @@ def test_net_validation_rejects_before_device_work(lib):
         with pytest.raises(B.BemfftError) as ei:
             B.Net(grid, dil[:layers])
         assert ei.value.status == B.EINVAL
+
+
+def test_node_count_limit(lib):
+    """Node counts whose [F][m] field index would overflow 32 bits are refused
+    before any node is read (the pointer below holds one node only)."""
+    L = lib
+    g = B.bemfft_grid()
+    g.dim = 3
+    for a in range(3):
+        g.n[a] = 16
+    g.h = 1.0 / 16
+    one = np.full(3, 0.5)
+    dp = ctypes.POINTER(ctypes.c_double)
+    out = ctypes.c_void_p()
+    for kernel, fields in ((B.NAVIER3D, 9), (B.LAPLACE3D, 4)):
+        m = (2 ** 31 - 1) // fields + 1
+        st = L.bemfft_plan_create(ctypes.byref(out), ctypes.byref(g), m, one.ctypes.data_as(dp),
+                                  one.ctypes.data_as(dp), None, kernel, 0.3, 1.0, None)
+        assert st == B.EINVAL, (kernel, st)
+        assert "node count" in B.last_error()
+    st = L.bemfft_plan_create(ctypes.byref(out), ctypes.byref(g), 0, one.ctypes.data_as(dp), one.ctypes.data_as(dp),
+                              None, B.LAPLACE3D, 0.3, 1.0, None)
+    assert st == B.EINVAL
+
+
+def test_binding_rejects_bad_tensors_before_any_call(lib):
+    """The binding checks device, dtype, contiguity and length itself: the
+    library trusts the sizes it is given.  CPU tensors, float32 vectors,
+    short vectors and a non-uint8 bc raise ValueError without a library
+    call (the fake handle would fail loudly if one were made)."""
+    torch = pytest.importorskip("torch")
+    fake = ctypes.c_void_p(1)
+    cpu = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        B.bemfft_apply(fake, cpu, cpu, cpu, n=10)
+    with pytest.raises(ValueError, match="torch tensor"):
+        B.bemfft_apply(fake, np.zeros(10), cpu, cpu, n=10)
+    with pytest.raises(ValueError, match="float64"):
+        B._f64(torch.zeros(10, dtype=torch.float32), 10, "q")
+    with pytest.raises(ValueError, match="elements"):
+        B.bemfft_apply(fake, torch.zeros(9, dtype=torch.float64), cpu, cpu, n=10)
+    with pytest.raises(ValueError, match="uint8"):
+        B._u8(torch.zeros(10, dtype=torch.int32), 10, "bc")
+    with pytest.raises(ValueError, match="contiguous"):
+        B._ptr(torch.zeros(10, 2, dtype=torch.float64).t())
+    with pytest.raises(ValueError, match="GPU"):
+        B.bemfft_solve(fake, torch.zeros(10, dtype=torch.uint8), cpu, cpu, n=10)
