@@ -626,6 +626,42 @@ def test_batch_solve_matches_single_solves(dev):
     batch.close()
 
 
+def test_batch_solve_on_reused_non_finite_memory(dev):
+    """Members that stop early in an Arnoldi cycle leave basis columns they
+    never wrote; the final update must not read them.  Device memory is first
+    filled with NaN, released to the runtime, and then reused by the batch's
+    basis: every member must still match its single solve."""
+    big = torch.full((256 * 1024 * 1024,), float("nan"), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    del big
+    torch.cuda.empty_cache()
+    specs = I.draw_stars(2, 2)
+    geoms = [I.star3d(16, specs[0], ntheta=256, nphi=512), I.star3d(24, specs[1], ntheta=384, nphi=768)]
+    plans = [B.Plan(g, B.LAPLACE3D, precision=B.FP64) for g in geoms]
+    batch = B.Batch(plans, nrhs=1, use_graph=False)
+    rng = np.random.default_rng(12)
+    known, bcs, singles = [], [], []
+    for g, pl in zip(geoms, plans):
+        bc = I.mixed_bc_upper(g)
+        u, q = I.random_harmonic_3d(g, rng)
+        kn = np.where(bc == 0, u, q)
+        known.append(kn)
+        bcs.append(bc)
+        xs, si = pl.solve(_t(bc, dev), _t(kn, dev), tol=1e-10)
+        singles.append((xs.cpu().numpy(), si))
+    assert singles[0][1]["iters"] != singles[1][1]["iters"]
+    x = torch.zeros(batch.total, dtype=torch.float64, device=dev)
+    st, info = batch.solve(_t(np.concatenate(bcs), dev), _t(np.concatenate(known), dev), x, tol=1e-10)
+    assert st == 0, info
+    x = x.cpu().numpy()
+    assert np.all(np.isfinite(x))
+    for k, (xs, si) in enumerate(singles):
+        o, n = batch.offsets[k], batch.lengths[k]
+        assert info[k]["true_relres"] <= 1e-10
+        assert np.linalg.norm(x[o:o + n] - xs) / np.linalg.norm(xs) < 1e-8
+    batch.close()
+
+
 def test_dirichlet_star_single_vs_batch_iterations(dev):
     """First-kind (all Dirichlet) problem: report-only comparison that the
     batched and single solves take the same path."""
