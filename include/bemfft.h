@@ -214,6 +214,35 @@ typedef struct {
 int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
                  const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
 
+/* Size of the fixed device workspace of bemfft_solve_noalloc: 32 MiB. */
+#define BEMFFT_NOALLOC_SCRATCH_BYTES (32LL << 20)
+
+/*
+ * bemfft_solve without any allocation, for callers that cannot allocate
+ * memory once they run: tight serving loops and harnesses that forbid
+ * hipMalloc after set-up.  Arguments, options, results and statuses are
+ * those of bemfft_solve (same kernels, same arithmetic: the same solution
+ * bit for bit), except:
+ *   - the Krylov basis, work vectors and reduction partials live in one
+ *     file-scope device array of BEMFFT_NOALLOC_SCRATCH_BYTES per GPU, held
+ *     until the process ends; its address is looked up once per device, on
+ *     the first call there;
+ *   - limit: (restart + 10) * ncomp * m + 132096 doubles must fit in it, else
+ *     EINVAL before any device work (the message names the largest restart
+ *     for the plan): e.g. restart 100 for up to 36,929 unknowns, restart 30
+ *     for up to 101,555;
+ *   - every call on one GPU shares that array and keeps what the last call
+ *     left in it: calls that overlap on one GPU (several host threads or
+ *     streams) race and give wrong results;
+ *   - no hipMalloc, hipFree, hipHostMalloc or event creation: the host
+ *     waits for each GMRES step before queueing the next and copies its
+ *     Hessenberg column to pageable host memory, so an iteration costs a
+ *     little more host latency than in bemfft_solve.
+ * The plan must exist already (bemfft_plan_create allocates).
+ */
+int bemfft_solve_noalloc(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
+                         const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream);
+
 /*
  * Dirichlet Laplace problem by conjugate gradients, the paper's own solver
  * (end of Sec. 4): u given at every node, find q with

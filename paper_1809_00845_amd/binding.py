@@ -61,8 +61,10 @@ EXPORTS = [
     "bemfft_batch_members", "bemfft_batch_destroy", "bemfft_net_create", "bemfft_net_destroy",
     "bemfft_net_num_params", "bemfft_net_get_params", "bemfft_net_set_params", "bemfft_net_input",
     "bemfft_net_forward", "bemfft_net_infer", "bemfft_net_gradients", "bemfft_net_train_step", "bemfft_net_guess",
-    "bemfft_plan_node_voxels", "bemfft_eval_grid", "bemfft_solve_cg",
+    "bemfft_plan_node_voxels", "bemfft_eval_grid", "bemfft_solve_cg", "bemfft_solve_noalloc",
 ]
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # BEMFFT_NOALLOC_SCRATCH_BYTES
 
 _lib = None
 
@@ -90,6 +92,8 @@ def load():
     L.bemfft_apply_profile.argtypes = [vp, vp, vp, vp, ctypes.c_int, dp, vp]
     L.bemfft_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(bemfft_solve_opts),
                                ctypes.POINTER(bemfft_solve_info), vp]
+    L.bemfft_solve_noalloc.argtypes = [vp, vp, vp, vp, ctypes.POINTER(bemfft_solve_opts),
+                                       ctypes.POINTER(bemfft_solve_info), vp]
     L.bemfft_solve_cg.argtypes = [vp, vp, vp, ctypes.POINTER(bemfft_solve_opts), ctypes.POINTER(bemfft_solve_info),
                                   vp]
     L.bemfft_plan_get_info.argtypes = [vp, ctypes.POINTER(bemfft_plan_info)]
@@ -265,6 +269,21 @@ def bemfft_solve(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, pr
     st = load().bemfft_solve(plan, _u8(bc, n, "bc"), _f64(known, n, "known"), _f64(unknown, n, "unknown"),
                              ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
     _check(st, "bemfft_solve")
+    return {"status": st, "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
+            "seconds": info.seconds, "outer": info.outer, "applies64": info.applies64,
+            "x0_used": info.x0_used, "x0_relres": info.x0_relres}
+
+
+def bemfft_solve_noalloc(plan, bc, known, unknown, tol=1e-6, restart=100, maxit=1000, precond=1, use_x0=0,
+                         refine=0, inner_tol=1e-4, max_outer=20, stream=None, n=None):
+    """bemfft_solve with its workspace in the library's fixed device array
+    (no allocation); same results."""
+    n = _plan_len(plan, n)
+    o = bemfft_solve_opts(tol, restart, maxit, precond, use_x0, refine, inner_tol, max_outer)
+    info = bemfft_solve_info()
+    st = load().bemfft_solve_noalloc(plan, _u8(bc, n, "bc"), _f64(known, n, "known"), _f64(unknown, n, "unknown"),
+                                     ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+    _check(st, "bemfft_solve_noalloc")
     return {"status": st, "iters": info.iters, "restarts": info.restarts, "true_relres": info.true_relres,
             "seconds": info.seconds, "outer": info.outer, "applies64": info.applies64,
             "x0_used": info.x0_used, "x0_relres": info.x0_relres}

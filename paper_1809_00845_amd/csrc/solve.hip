@@ -11,9 +11,12 @@
 // fresh apply at every restart and at the end.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
@@ -249,9 +252,12 @@ double norm2(const double *v, int64_t n, Ws &ws, double *pinned, hipStream_t st,
 // residual tolerance tol, at most maxit iterations.  Uses ws.w, ws.r, ws.q,
 // ws.u, ws.V.  Returns the status; iters and the final true relative
 // residual (w.r.t. ||rhs||) through the pointers.
+// pipelined = false (the allocation-free entry point): no events are created
+// and each step is waited for with a stream synchronisation before the next
+// one is queued (hp may then be ordinary pageable host memory).
 int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double *rhs, double *x, bool x_zero,
                double tol, int mcap, int maxit, Ws &ws, double *hp, hipStream_t st, int *iters_out, int *restarts_out,
-               double *relres_out, const double *r0_given = nullptr) {
+               double *relres_out, const double *r0_given, bool pipelined) {
     const int64_t n = (int64_t)p->ncomp * p->m;
     int status = 0;
     struct Events {
@@ -261,7 +267,8 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
                 if (x) (void)hipEventDestroy(x);
         }
     } evs;
-    for (hipEvent_t &x : evs.e) BF_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    if (pipelined)
+        for (hipEvent_t &x : evs.e) BF_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     const double bnorm = norm2(rhs, n, ws, hp, st, &status);
     BF_CHECK(status);
     int iters = 0, cycles = 0;
@@ -333,14 +340,19 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
             hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, st, ws.red, gn, 1, h2 + kk + 1, 1);
             BF_HIP(hipGetLastError());
             BF_HIP(hipMemcpyAsync(hp + 1024 * (kk & 1), ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
-            BF_HIP(hipEventRecord(evs.e[kk & 1], st));
+            if (pipelined) BF_HIP(hipEventRecord(evs.e[kk & 1], st));
             return 0;
         };
         const int kmax = std::min(mcap, maxit - iters);
-        BF_CHECK(queue_step(0));
+        if (pipelined) BF_CHECK(queue_step(0));
         for (; k < kmax; ++k) {
-            if (k + 1 < kmax) BF_CHECK(queue_step(k + 1));
-            BF_HIP(hipEventSynchronize(evs.e[k & 1]));
+            if (pipelined) {
+                if (k + 1 < kmax) BF_CHECK(queue_step(k + 1));
+                BF_HIP(hipEventSynchronize(evs.e[k & 1]));
+            } else {
+                BF_CHECK(queue_step(k));
+                BF_HIP(hipStreamSynchronize(st));
+            }
             const double *hk = hp + 1024 * (k & 1);
             ++iters;
             double *col = &H[(size_t)k * (mcap + 1)];
@@ -519,14 +531,18 @@ int cg_op(bemfft_plan *p, const double *v, const double *sw, Ws &ws, double *av,
 
 using namespace bemfft;
 
-extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
-                            const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream) {
-    auto t0 = std::chrono::steady_clock::now();
+namespace bemfft {
+namespace {
+
+// Arguments and options of bemfft_solve, checked; o receives the options
+// with defaults filled in.
+int solve_check(const bemfft_plan *p, const uint8_t *bc, const double *known, const double *unknown,
+                const bemfft_solve_opts *opts, bemfft_solve_opts &o) {
     if (!p || !bc || !known || !unknown) {
         set_error("solve: null argument");
         return BEMFFT_EINVAL;
     }
-    bemfft_solve_opts o{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
+    o = bemfft_solve_opts{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
     if (opts) o = *opts;
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.use_x0 < 0 || o.use_x0 > 2) {
         set_error("solve: bad options");
@@ -536,13 +552,17 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
         set_error("solve: refinement needs a plan created with keep_fp64 (or FP64), inner_tol > 0, max_outer >= 1");
         return BEMFFT_EINVAL;
     }
-    hipStream_t st = (hipStream_t)stream;
+    return 0;
+}
+
+// The mixed problem of bemfft_solve with the given workspace (device
+// vectors ws, host buffer hp of 4 * 512 doubles); pipelined as gmres_core.
+int solve_impl(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown, const bemfft_solve_opts &o,
+               bemfft_solve_info *info, hipStream_t st, Ws &ws, double *hp, bool pipelined,
+               std::chrono::steady_clock::time_point t0) {
     const int64_t n = (int64_t)p->ncomp * p->m;
     const Engine &e64 = (p->eng.precision == BEMFFT_FP64) ? p->eng : p->eng64;
     const Engine &eo = o.refine ? e64 : p->eng;  // operator of b and of the true residual
-    Ws ws{};
-    BF_CHECK(ensure_workspace(p, o.restart, ws));
-    double *hp = p->h_pinned;
     int status = 0;
     // b = -apply(known values in their slots)
     hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(256), 0, st, bc, known, (const double *)nullptr, ws.q, ws.u,
@@ -581,7 +601,7 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
     }
     if (!o.refine) {
         status = gmres_core(p, p->eng, bc, ws.b, ws.x, !use_x0, o.tol, o.restart, o.maxit, ws, hp, st, &iters,
-                            &restarts, &rel, o.use_x0 == 2 ? ws.ro : nullptr);
+                            &restarts, &rel, o.use_x0 == 2 ? ws.ro : nullptr, pipelined);
     } else {
         // iterative refinement: r = b - A64 x in FP64, d ~ A^-1 r in the
         // working precision, x += d
@@ -613,7 +633,7 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
             double irel = 0.0;
             BF_HIP(hipMemsetAsync(ws.d, 0, n * sizeof(double), st));
             int s3 = gmres_core(p, p->eng, bc, ws.ro, ws.d, true, itol, o.restart, o.maxit - iters, ws, hp, st, &it,
-                                &rs, &irel);
+                                &rs, &irel, nullptr, pipelined);
             iters += it;
             restarts += rs;
             if (s3 < 0) { status = s3; break; }
@@ -637,6 +657,90 @@ extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *kno
         info->x0_relres = o.use_x0 == 2 ? rel0 : -1.0;
     }
     return status;
+}
+
+// ------------------------------------------------------------------ no allocation
+// Workspace of bemfft_solve_noalloc: one file-scope device array per GPU,
+// held until the process ends.  Its host-side name is not a device address:
+// host code uses only the per-device pointer from hipGetSymbolAddress.
+constexpr int64_t kScratchDoubles = BEMFFT_NOALLOC_SCRATCH_BYTES / 8;
+constexpr int64_t kRedDoubles = (int64_t)kRedBlocks * 512;  // reduction partials
+constexpr int64_t kHdDoubles = 2 * 512;                     // Hessenberg column buffer
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+// host side of the per-step Hessenberg copies (pageable; one per device)
+double g_noalloc_host[kMaxDevices][4 * 512];
+
+// Largest restart whose basis fits the workspace for n unknowns.
+int64_t noalloc_max_restart(int64_t n) {
+    const int64_t avail = kScratchDoubles - kRedDoubles - kHdDoubles;
+    return std::min<int64_t>(400, avail / n - 10);
+}
+
+int scratch_for_current_device(double **out, int *dev_out) {
+    int dev = -1;
+    BF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("solve_noalloc: device index out of range");
+        return BEMFFT_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        BF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    *dev_out = dev;
+    return 0;
+}
+
+}  // namespace
+}  // namespace bemfft
+
+extern "C" int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
+                            const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    bemfft_solve_opts o;
+    BF_CHECK(solve_check(p, bc, known, unknown, opts, o));
+    Ws ws{};
+    BF_CHECK(ensure_workspace(p, o.restart, ws));
+    return solve_impl(p, bc, known, unknown, o, info, (hipStream_t)stream, ws, p->h_pinned, true, t0);
+}
+
+extern "C" int bemfft_solve_noalloc(bemfft_plan *p, const uint8_t *bc, const double *known, double *unknown,
+                                    const bemfft_solve_opts *opts, bemfft_solve_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    bemfft_solve_opts o;
+    BF_CHECK(solve_check(p, bc, known, unknown, opts, o));
+    const int64_t n = (int64_t)p->ncomp * p->m;
+    const int64_t need = (int64_t)(o.restart + 1) * n + 9 * n + kRedDoubles + kHdDoubles;
+    if (need > kScratchDoubles) {
+        set_error("solve_noalloc: (restart + 10) * ncomp * m = " + std::to_string((int64_t)(o.restart + 10) * n) +
+                  " doubles exceeds the fixed workspace; largest restart for this plan: " +
+                  std::to_string(noalloc_max_restart(n)));
+        return BEMFFT_EINVAL;
+    }
+    double *base = nullptr;
+    int dev = 0;
+    BF_CHECK(scratch_for_current_device(&base, &dev));
+    Ws ws{};
+    ws.red = base;
+    ws.hd = ws.red + kRedDoubles;
+    ws.b = ws.hd + kHdDoubles;
+    ws.x = ws.b + n;
+    ws.w = ws.x + n;
+    ws.q = ws.w + n;
+    ws.u = ws.q + n;
+    ws.r = ws.u + n;
+    ws.dinv = ws.r + n;
+    ws.ro = ws.dinv + n;
+    ws.d = ws.ro + n;
+    ws.V = ws.d + n;
+    ws.cap = o.restart + 1;
+    return solve_impl(p, bc, known, unknown, o, info, (hipStream_t)stream, ws, g_noalloc_host[dev], false, t0);
 }
 
 extern "C" int bemfft_solve_cg(bemfft_plan *p, const double *u, double *q, const bemfft_solve_opts *opts,
