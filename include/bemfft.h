@@ -84,8 +84,20 @@ typedef struct bemfft_plan bemfft_plan; /* opaque; owns all device state */
 typedef enum { BEMFFT_LAPLACE2D = 0, BEMFFT_LAPLACE3D = 1, BEMFFT_NAVIER3D = 2, BEMFFT_HALFSPACE = 3 } bemfft_kernel;
 
 /* Arithmetic of the transforms and the spectral product.  Kernel spectra are
- * always computed in FP64 and rounded to the working precision. */
-typedef enum { BEMFFT_FP64 = 0, BEMFFT_FP32 = 1 } bemfft_precision;
+ * always computed in FP64 and rounded to the working precision.
+ *   BEMFFT_FP64, BEMFFT_FP32: every transform and product in that precision.
+ *   BEMFFT_BF16_MFMA (3D plans only): the arrays that carry the apply's HBM
+ *     traffic -- the field transforms after the y pass, the results of the
+ *     inverse z pass and the kernel spectra -- are stored in BF16; the z
+ *     transforms run as two stages of dense 16 x 16 DFT matrix products on
+ *     the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation); the x
+ *     and y transforms, the spectral products and the gather are FP32, node
+ *     data and results FP64.  Stated error of an apply against the FP64
+ *     operator: <= 2e-3 of the term magnitudes (one BF16 unit round-off;
+ *     measured 1e-4 to 5e-4); use it for the inner solves of an
+ *     FP64-refined solve (bemfft_solve refine = 1).  Batches of 16-bit plans
+ *     are not supported. */
+typedef enum { BEMFFT_FP64 = 0, BEMFFT_FP32 = 1, BEMFFT_BF16_MFMA = 2 } bemfft_precision;
 
 /* Free term c of eq. (4)/(8): 1/2 (smooth boundary), user values, or the
  * implicit c_j = -D[1]_j (Navier: C_j = -[D e_1, D e_2, D e_3]_j). */

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbemfft.so")
 
 LAPLACE2D, LAPLACE3D, NAVIER3D, HALFSPACE = 0, 1, 2, 3
-FP64, FP32 = 0, 1
+FP64, FP32, BF16_MFMA = 0, 1, 2
 C_HALF, C_USER, C_IMPLICIT = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBREAKDOWN, ENOCONV = 0, -1, -2, -3, -4, -5, 1
 

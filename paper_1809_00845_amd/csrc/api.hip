@@ -105,6 +105,16 @@ std::vector<cx<R>> twiddle_table(int64_t p) {
     return t;
 }
 
+// BF16 bit pattern of v: v rounded to FP32, then to 8 mantissa bits with
+// round to nearest, ties to even (v is finite).
+uint16_t bf16_bits(double v) {
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 int64_t auto_pad(int64_t n) {
     for (int64_t s : kSizes)
         if (s >= 2 * n) return s;
@@ -140,12 +150,12 @@ static int upload_tw(Engine *e, const bemfft_plan *p) {
 }
 
 int upload_twiddles(Engine *e, const bemfft_plan *p) {
-    return e->precision == BEMFFT_FP32 ? upload_tw<float>(e, p) : upload_tw<double>(e, p);
+    return e->precision == BEMFFT_FP64 ? upload_tw<double>(e, p) : upload_tw<float>(e, p);
 }
 
 int alloc_workspace(bemfft_plan *p, Engine *e) {
     BF_CHECK(alloc_intermediates(p, e->precision, e));
-    const size_t spec = (size_t)p->K * p->H[0] * p->H[1] * p->H[2] * e->creal;
+    const size_t spec = (size_t)p->K * p->H[0] * p->H[1] * p->H[2] * e->sreal;
     if (hipMalloc(&e->spec, spec) != hipSuccess) {
         set_error("hipMalloc of the spectra failed");
         return BEMFFT_ENOMEM;
@@ -198,10 +208,14 @@ void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, Ap
 
 int alloc_intermediates(const bemfft_plan *p, int precision, Engine *e) {
     e->precision = precision;
-    e->creal = precision == BEMFFT_FP32 ? 4 : 8;
-    const size_t cb = 2 * e->creal;
+    e->creal = precision == BEMFFT_FP64 ? 8 : 4;
+    e->sreal = precision == BEMFFT_FP64 ? 8 : (precision == BEMFFT_FP32 ? 4 : 2);
+    const size_t cb = 2 * e->creal, sb = 2 * e->sreal;
     const size_t rows = (size_t)p->H[0] * p->nzo * p->P[1];
-    const size_t ysz = (size_t)p->F * rows * cb, zsz = (size_t)p->O * rows * cb;
+    // Y also holds the inverse y pass's rows in the arithmetic precision:
+    // O nzo ny Hx complex values, never more than F Hx nzo Py stored ones
+    const size_t ysz = std::max((size_t)p->F * rows * sb, (size_t)p->O * p->nzo * p->n[1] * p->H[0] * cb);
+    const size_t zsz = (size_t)p->O * rows * sb;
     const size_t vsz = (size_t)p->F * p->m * e->creal;
     const size_t xsz = std::max<size_t>(1, (size_t)p->nd * p->F * p->H[0] * cb);
     if (hipMalloc(&e->Y, ysz) != hipSuccess || hipMalloc(&e->Z, zsz) != hipSuccess ||
@@ -317,7 +331,14 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     }
     const int prec = opts ? (int)opts->precision : BEMFFT_FP64;
     const int cmode = opts ? (int)opts->c_mode : BEMFFT_C_IMPLICIT;
-    if (prec != BEMFFT_FP64 && prec != BEMFFT_FP32) { set_error("unknown precision"); return BEMFFT_EINVAL; }
+    if (prec != BEMFFT_FP64 && prec != BEMFFT_FP32 && prec != BEMFFT_BF16_MFMA) {
+        set_error("unknown precision");
+        return BEMFFT_EINVAL;
+    }
+    if (prec == BEMFFT_BF16_MFMA && ki.dim != 3) {
+        set_error("the 16-bit form runs the z transforms on the matrix cores: 3D plans only");
+        return BEMFFT_EINVAL;
+    }
     if (cmode < 0 || cmode > 2) { set_error("unknown c_mode"); return BEMFFT_EINVAL; }
     if (cmode == BEMFFT_C_USER && !(opts && opts->c_user)) { set_error("C_USER needs c_user"); return BEMFFT_EINVAL; }
     hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
@@ -449,6 +470,7 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     Engine e64;
     e64.precision = BEMFFT_FP64;
     e64.creal = 8;
+    e64.sreal = 8;
     int status = alloc_workspace(p, &e64);
     if (!status) status = upload_twiddles(&e64, p);
     if (!status) status = build_spectra(p, &e64, nullptr, st);
@@ -489,21 +511,31 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
         p->eng = e64;
         p->has64 = true;
     } else {
-        Engine e32;
-        e32.precision = BEMFFT_FP32;
-        e32.creal = 4;
-        status = alloc_workspace(p, &e32);
+        Engine e32;  // FP32 or 16-bit working engine
+        e32.precision = prec;
+        status = alloc_workspace(p, &e32);  // sets the element sizes
         if (!status) status = upload_twiddles(&e32, p);
         if (!status) {
+            // the FP64 spectra rounded once to the stored precision
             const int64_t n = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2];
             std::vector<double> tmp(n);
-            std::vector<float> tmpf(n);
-            if (hipMemcpy(tmp.data(), e64.spec, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
-                (std::transform(tmp.begin(), tmp.end(), tmpf.begin(), [](double v) { return (float)v; }),
-                 hipMemcpy(e32.spec, tmpf.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)) {
+            std::vector<float> tmpf;
+            std::vector<uint16_t> tmph;
+            const void *src = nullptr;
+            if (hipMemcpy(tmp.data(), e64.spec, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
                 status = BEMFFT_EDEVICE;
-                set_error("spectrum conversion failed");
+            } else if (prec == BEMFFT_FP32) {
+                tmpf.resize(n);
+                std::transform(tmp.begin(), tmp.end(), tmpf.begin(), [](double v) { return (float)v; });
+                src = tmpf.data();
+            } else {
+                tmph.resize(n);
+                std::transform(tmp.begin(), tmp.end(), tmph.begin(), bf16_bits);
+                src = tmph.data();
             }
+            if (!status && hipMemcpy(e32.spec, src, n * e32.sreal, hipMemcpyHostToDevice) != hipSuccess)
+                status = BEMFFT_EDEVICE;
+            if (status) set_error("spectrum conversion failed");
         }
         if (status == 0 && opts && opts->keep_fp64) {
             p->eng64 = e64;  // the refinement's FP64 operator
@@ -516,8 +548,9 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     }
     if (hipStreamSynchronize(st) != hipSuccess) { set_error("plan: stream sync failed"); return BEMFFT_EDEVICE; }
     const int tune = opts ? opts->autotune : 0;
-    if (tune == 2) p->zsched = 1;
-    else if (tune == 1 && p->dim == 3) BF_CHECK(autotune_zsched(p, st));
+    // the 16-bit z pass has one schedule (its transforms are matrix products)
+    if (tune == 2 && prec != BEMFFT_BF16_MFMA) p->zsched = 1;
+    else if (tune == 1 && p->dim == 3 && prec != BEMFFT_BF16_MFMA) BF_CHECK(autotune_zsched(p, st));
     p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return 0;
 }
@@ -706,7 +739,7 @@ int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {
     info->nspectra = p->K;
     info->noutputs = p->O;
     info->workspace_bytes = (int64_t)(p->eng.bytes + p->eng64.bytes);
-    info->spectra_bytes = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2] * (int64_t)p->eng.creal;
+    info->spectra_bytes = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2] * (int64_t)p->eng.sreal;
     info->spectrum_parity_residual = p->parity_resid;
     info->plan_seconds = p->plan_seconds;
     info->zsched = p->zsched;

@@ -79,6 +79,24 @@ constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 constexpr int mini(int a, int b) { return a < b ? a : b; }
 constexpr int kMaxPx = 512;          // largest padded length along x
 
+// Complex value stored in 16 bits per part (the intermediates Y and Z of the
+// 16-bit form); arithmetic stays FP32.
+struct alignas(4) cbf16 {
+    __bf16 x, y;
+};
+// Storage conversions: identity for cx<R>, FP32 <-> BF16 (round to nearest
+// even) for cbf16.
+template <typename S, typename R>
+__device__ __forceinline__ S to_store(cx<R> v) {
+    if constexpr (std::is_same<S, cbf16>::value) return cbf16{(__bf16)(float)v.x, (__bf16)(float)v.y};
+    else return v;
+}
+template <typename R, typename S>
+__device__ __forceinline__ cx<R> from_store(S v) {
+    if constexpr (std::is_same<S, cbf16>::value) return cx<R>{(R)(float)v.x, (R)(float)v.y};
+    else return v;
+}
+
 // (k x) mod p for 0 <= k x < 2^24, with a float estimate of the quotient.
 __device__ __forceinline__ int mod_small(int kx, int x, int p, float inv_p) {
     const int prod = kx * x;
@@ -257,7 +275,7 @@ struct FwdCfg {
 
 // XG: kx per thread in the direct DFT (1, or 2 on plans whose short rows
 // hold few nodes, where one node load then serves two kx).
-template <typename R, int PY, int KIND, int XG_>
+template <typename R, int PY, int KIND, int XG_, typename YS = cx<R>>
 __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, const int by, const int bz) {
     if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
     using Cfg = FwdCfg<R, PY, KIND>;
@@ -338,15 +356,15 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
     }
     fft_regs<R, PY, -1>(x, pb, tw, t);
     if (kx < a.hx) {
-        cx<R> *Y = static_cast<cx<R> *>(a.Y) + ((size_t)(f * a.hx + kx) * a.nzo + zz) * PY;
+        YS *Y = static_cast<YS *>(a.Y) + ((size_t)(f * a.hx + kx) * a.nzo + zz) * PY;
 #pragma unroll
-        for (int e = 0; e < E; ++e) Y[t + e * TPP] = x[e];
+        for (int e = 0; e < E; ++e) Y[t + e * TPP] = to_store<YS>(x[e]);
     }
 }
 
-template <typename R, int PY, int KIND, int XG>
+template <typename R, int PY, int KIND, int XG, typename YS = cx<R>>
 __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
-    fwd_xy_body<R, PY, KIND, XG>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+    fwd_xy_body<R, PY, KIND, XG, YS>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -568,7 +586,7 @@ struct InvYCfg {
 
 // all_rows = 0 (the apply): only rows that hold nodes are stored, the
 // gather reads nothing else; all_rows = 1 (the grid evaluation): every row.
-template <typename R, int PY, int KIND>
+template <typename R, int PY, int KIND, typename ZS = cx<R>>
 __device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, const int by, const int all_rows) {
     if (by >= a.nzo) return;  // batched: a member with fewer occupied planes
     using Cfg = InvYCfg<R, PY, KIND>;
@@ -587,9 +605,9 @@ __device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, con
     const int o = pen / KXC, kx = kx0 + pen % KXC;
     cx<R> x[E];
     if (kx < a.hx) {
-        const cx<R> *Zr = static_cast<const cx<R> *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
+        const ZS *Zr = static_cast<const ZS *>(a.Z) + ((size_t)(o * a.hx + kx) * a.nzo + zz) * PY;
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = Zr[t + e * TPP];
+        for (int e = 0; e < E; ++e) x[e] = from_store<R>(Zr[t + e * TPP]);
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = {R(0), R(0)};
@@ -614,9 +632,9 @@ __device__ __forceinline__ void inv_y_body(const ApplyArgs &a, const int bx, con
     }
 }
 
-template <typename R, int PY, int KIND>
+template <typename R, int PY, int KIND, typename ZS = cx<R>>
 __global__ __launch_bounds__((InvYCfg<R, PY, KIND>::NT)) void k_inv_y(ApplyArgs a, int all_rows) {
-    inv_y_body<R, PY, KIND>(a, blockIdx.x, blockIdx.y, all_rows);
+    inv_y_body<R, PY, KIND, ZS>(a, blockIdx.x, blockIdx.y, all_rows);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -829,20 +847,20 @@ __global__ __launch_bounds__(256) void kb_gather(const ApplyArgs *members, const
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename R, int PY, int KIND>
+template <typename R, int PY, int KIND, typename YS = cx<R>>
 int launch_fwd(const ApplyArgs &a, hipStream_t st) {
     using Cfg = FwdCfg<R, PY, KIND>;
     dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
-    if (a.fwd_xg == 2) hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 2>), grid, dim3(Cfg::NT), 0, st, a);
-    else hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 1>), grid, dim3(Cfg::NT), 0, st, a);
+    if (a.fwd_xg == 2) hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 2, YS>), grid, dim3(Cfg::NT), 0, st, a);
+    else hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 1, YS>), grid, dim3(Cfg::NT), 0, st, a);
     BF_HIP(hipGetLastError());
     return 0;
 }
-template <typename R, int PY, int KIND>
+template <typename R, int PY, int KIND, typename ZS = cx<R>>
 int launch_inv_y(const ApplyArgs &a, int all_rows, hipStream_t st) {
     using Cfg = InvYCfg<R, PY, KIND>;
     dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
-    hipLaunchKernelGGL((k_inv_y<R, PY, KIND>), grid, dim3(Cfg::NT), 0, st, a, all_rows);
+    hipLaunchKernelGGL((k_inv_y<R, PY, KIND, ZS>), grid, dim3(Cfg::NT), 0, st, a, all_rows);
     BF_HIP(hipGetLastError());
     return 0;
 }

@@ -317,6 +317,10 @@ int bemfft_batch_create(bemfft_batch **out, bemfft_plan *const *plans, int nplan
             set_error("batch_create: null plan");
             return BEMFFT_EINVAL;
         }
+        if (plans[i]->eng.precision == BEMFFT_BF16_MFMA) {
+            set_error("batch_create: batches of 16-bit plans are not supported");
+            return BEMFFT_EINVAL;
+        }
         if (plans[i]->kernel != plans[0]->kernel || plans[i]->eng.precision != plans[0]->eng.precision) {
             set_error("batch_create: plans must share the kernel family and the working precision");
             return BEMFFT_EINVAL;

@@ -51,9 +51,10 @@ inline KindInfo kind_info(int kernel) {
 
 // Device state of one working precision.
 struct Engine {
-    int precision = BEMFFT_FP64;  // BEMFFT_FP64 or BEMFFT_FP32
-    size_t creal = 8;             // bytes per real
-    void *spec = nullptr;         // [K][Hx][Hy][Hz] reals
+    int precision = BEMFFT_FP64;  // BEMFFT_FP64, BEMFFT_FP32 or BEMFFT_BF16_MFMA
+    size_t creal = 8;             // bytes per real of the arithmetic (twiddles, fields, rows)
+    size_t sreal = 8;             // bytes per real of the stored Y, Z and spectra
+    void *spec = nullptr;         // [K][Hx][Hy][Hz] reals (sreal bytes each)
     void *twx = nullptr;          // [Px] complex, exp(-2 pi i t / Px)
     void *twy = nullptr;          // [Py]
     void *twz = nullptr;          // [Pz]
