@@ -155,7 +155,9 @@ int upload_twiddles(Engine *e, const bemfft_plan *p) {
 
 int alloc_workspace(bemfft_plan *p, Engine *e) {
     BF_CHECK(alloc_intermediates(p, e->precision, e));
-    const size_t spec = (size_t)p->K * p->H[0] * p->H[1] * p->H[2] * e->sreal;
+    // 16-bit spectra: kz rows padded to a multiple of 8 values (16-byte runs)
+    e->hzs = e->precision == BEMFFT_BF16_MFMA ? (p->H[2] + 7) / 8 * 8 : p->H[2];
+    const size_t spec = (size_t)p->K * p->H[0] * p->H[1] * e->hzs * e->sreal;
     if (hipMalloc(&e->spec, spec) != hipSuccess) {
         set_error("hipMalloc of the spectra failed");
         return BEMFFT_ENOMEM;
@@ -175,6 +177,7 @@ void fill_apply_args(const bemfft_plan *p, const Engine &e, const Engine &ws, Ap
     a.hx = (int)p->H[0];
     a.hy = (int)p->H[1];
     a.hz = (int)p->H[2];
+    a.hzs = (int)e.hzs;
     a.z0 = (int)p->z0;
     a.nzo = (int)p->nzo;
     a.m = (int)p->m;
@@ -529,11 +532,15 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
                 std::transform(tmp.begin(), tmp.end(), tmpf.begin(), [](double v) { return (float)v; });
                 src = tmpf.data();
             } else {
-                tmph.resize(n);
-                std::transform(tmp.begin(), tmp.end(), tmph.begin(), bf16_bits);
+                // rows of hzs >= Hz values, zero beyond Hz
+                const int64_t hz = p->H[2], rows = n / hz;
+                tmph.assign((size_t)rows * e32.hzs, 0);
+                for (int64_t rw = 0; rw < rows; ++rw)
+                    for (int64_t k = 0; k < hz; ++k) tmph[(size_t)rw * e32.hzs + k] = bf16_bits(tmp[(size_t)rw * hz + k]);
                 src = tmph.data();
             }
-            if (!status && hipMemcpy(e32.spec, src, n * e32.sreal, hipMemcpyHostToDevice) != hipSuccess)
+            const size_t sbytes = (size_t)p->K * p->H[0] * p->H[1] * e32.hzs * e32.sreal;
+            if (!status && hipMemcpy(e32.spec, src, sbytes, hipMemcpyHostToDevice) != hipSuccess)
                 status = BEMFFT_EDEVICE;
             if (status) set_error("spectrum conversion failed");
         }
@@ -739,7 +746,7 @@ int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {
     info->nspectra = p->K;
     info->noutputs = p->O;
     info->workspace_bytes = (int64_t)(p->eng.bytes + p->eng64.bytes);
-    info->spectra_bytes = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2] * (int64_t)p->eng.sreal;
+    info->spectra_bytes = (int64_t)p->K * p->H[0] * p->H[1] * p->eng.hzs * (int64_t)p->eng.sreal;
     info->spectrum_parity_residual = p->parity_resid;
     info->plan_seconds = p->plan_seconds;
     info->zsched = p->zsched;

@@ -38,6 +38,7 @@ struct ApplyArgs {
     int nx, ny, nz;
     int px, py, pz;
     int hx, hy, hz;
+    int hzs;          // stored kz row length of the spectra (hz, or padded)
     int z0, nzo;
     int m;
     int zsched;       // radix schedule of the z pass (0 or 1)

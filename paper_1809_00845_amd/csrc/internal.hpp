@@ -54,7 +54,8 @@ struct Engine {
     int precision = BEMFFT_FP64;  // BEMFFT_FP64, BEMFFT_FP32 or BEMFFT_BF16_MFMA
     size_t creal = 8;             // bytes per real of the arithmetic (twiddles, fields, rows)
     size_t sreal = 8;             // bytes per real of the stored Y, Z and spectra
-    void *spec = nullptr;         // [K][Hx][Hy][Hz] reals (sreal bytes each)
+    int64_t hzs = 1;              // stored length of a spectrum's kz row (>= Hz)
+    void *spec = nullptr;         // [K][Hx][Hy][hzs] reals (sreal bytes each)
     void *twx = nullptr;          // [Px] complex, exp(-2 pi i t / Px)
     void *twy = nullptr;          // [Py]
     void *twz = nullptr;          // [Pz]

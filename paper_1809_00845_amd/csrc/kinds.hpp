@@ -85,4 +85,37 @@ struct Terms<3> {  // elastic half-space: u_a = sum_b K_ab * sigma_b, 9 terms
     }
 };
 
+// Spectral components that multiply field f, in term order.
+template <int KIND>
+__host__ __device__ constexpr int field_ncomp(int f) {
+    int n = 0;
+    for (int t = 0; t < Terms<KIND>::N; ++t)
+        if (Terms<KIND>::f(t) == f) ++n;
+    return n;
+}
+template <int KIND>
+__host__ __device__ constexpr int field_comp(int f, int i) {
+    int n = 0;
+    for (int t = 0; t < Terms<KIND>::N; ++t)
+        if (Terms<KIND>::f(t) == f) {
+            if (n == i) return Terms<KIND>::c(t);
+            ++n;
+        }
+    return -1;
+}
+// Position of term t among the terms of its field.
+template <int KIND>
+__host__ __device__ constexpr int term_slot(int t) {
+    int n = 0;
+    for (int u = 0; u < t; ++u)
+        if (Terms<KIND>::f(u) == Terms<KIND>::f(t)) ++n;
+    return n;
+}
+template <int KIND>
+__host__ __device__ constexpr int max_field_ncomp() {
+    int m = 0;
+    for (int f = 0; f < Terms<KIND>::F; ++f) m = field_ncomp<KIND>(f) > m ? field_ncomp<KIND>(f) : m;
+    return m;
+}
+
 }  // namespace bemfft

@@ -44,6 +44,7 @@ namespace bemfft {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // One 16 x 16 complex tile in the accumulator layout.
 struct MTile {
@@ -102,6 +103,10 @@ struct Z16Cfg {
     static constexpr int LS = PPB + 1;                   // staging row stride (padded)
     static constexpr int QPR = PPB / 4;                  // 16-byte runs per row
     static constexpr int LMAX = (HALF * QPR + NT - 1) / NT;
+    static constexpr int HZS = (P / 2 + 1 + 7) / 8 * 8;  // stored kz row of a spectrum
+    static constexpr int NCF = max_field_ncomp<KIND>();  // spectra per field
+    static constexpr int SRUNS = HZS / 8;                // 16-byte runs per spectrum row
+    static constexpr int SMAX = (NCF * PPB * SRUNS + NT - 1) / NT;
     static_assert(N2 * 16 == P && PPB % 4 == 0, "length and block shape");
 };
 
@@ -213,6 +218,40 @@ __device__ __forceinline__ bf16x8 bf16x8_from_words(unsigned w0, unsigned w1, un
     return x.v;
 }
 
+// Loads of field f into registers: its rows of Y for the block's pencils
+// and the rows of the spectra that multiply it, all as 16-byte runs.
+template <int P, int KIND>
+__device__ __forceinline__ void z16_load_field(const int f, const ApplyArgs &a, const unsigned *Y,
+                                               const uint16_t *spec, size_t fstride, int nrun, int kx, int ky0,
+                                               u32x4 (&pre)[Z16Cfg<P, KIND>::LMAX],
+                                               u32x4 (&spre)[Z16Cfg<P, KIND>::SMAX]) {
+    using C = Z16Cfg<P, KIND>;
+    constexpr int PPB = C::PPB, QPR = C::QPR, NT = C::NT;
+    const int tid = threadIdx.x;
+    const unsigned *Yf = Y + (size_t)f * fstride;
+    // every lane loads (runs past the end repeat the last one) so that the
+    // loads stay in flight in registers; only the LDS writes are conditional
+#pragma unroll
+    for (int k = 0; k < C::LMAX; ++k) {
+        const int it = min(tid + k * NT, nrun - 1);
+        const int zz = it / QPR, q = it % QPR;
+        pre[k] = *reinterpret_cast<const u32x4 *>(Yf + (size_t)zz * a.py + 4 * q);
+    }
+    const int ncf = field_ncomp<KIND>(f);  // f is a constant once the field loop is unrolled
+    static_assert(C::NCF <= 3, "at most three spectra per field");
+#pragma unroll
+    for (int k = 0; k < C::SMAX; ++k) {
+        const int it = min(tid + k * NT, ncf * PPB * C::SRUNS - 1);
+        const int slot = it / (PPB * C::SRUNS), pen = (it / C::SRUNS) % PPB, q = it % C::SRUNS;
+        int comp = field_comp<KIND>(f, 0);
+        if (ncf > 1) comp = slot == 1 ? field_comp<KIND>(f, 1) : comp;
+        if (ncf > 2) comp = slot == 2 ? field_comp<KIND>(f, 2) : comp;
+        const int ky = ky0 + pen;
+        const int kyp = ky < a.hy ? ky : a.py - ky;
+        spre[k] = *reinterpret_cast<const u32x4 *>(spec + ((size_t)(comp * a.hx + kx) * a.hy + kyp) * C::HZS + 8 * q);
+    }
+}
+
 // One block: kx and PPB consecutive ky (ky0 = by * PPB).  One-dimensional
 // grid with the XCD-aware order of k_zpass.
 template <int P, int KIND>
@@ -226,6 +265,8 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
     __shared__ bf16x8 ops[2 * C::NOPS * 64];
     __shared__ cx<float> twf[NE * 64], twi[NE * 64];
     __shared__ unsigned kzo[NE * 64];
+    // the field's spectrum rows for the block's pencils: [slot][pencil][kz]
+    __shared__ uint16_t sspec[C::NCF * PPB * C::HZS];
     const int tid = threadIdx.x, lane = tid % 64;
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const int g = lane / 16, c = lane % 16;
@@ -243,22 +284,10 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
     const size_t fstride = (size_t)a.hx * a.nzo * a.py;  // complex values per field
     const unsigned *Y = static_cast<const unsigned *>(a.Y) + (size_t)kx * a.nzo * a.py + ky0;
     const uint16_t *spec = static_cast<const uint16_t *>(a.spec);
-    const size_t cstride = (size_t)a.hx * a.hy * a.hz;
     const int nrun = a.nzo * QPR;  // 16-byte runs of one field
 
-    uint4 pre[C::LMAX];
-    auto load_field = [&](int f) {
-        const unsigned *Yf = Y + (size_t)f * fstride;
-#pragma unroll
-        for (int k = 0; k < C::LMAX; ++k) {
-            const int it = tid + k * NT;
-            if (it < nrun) {
-                const int zz = it / QPR, q = it % QPR;
-                pre[k] = *reinterpret_cast<const uint4 *>(Yf + (size_t)zz * a.py + 4 * q);
-            }
-        }
-    };
-    load_field(0);
+    u32x4 pre[C::LMAX], spre[C::SMAX];
+    z16_load_field<P, KIND>(0, a, Y, spec, fstride, nrun, kx, ky0, pre, spre);
 
     MTile acc[UPW][CT][O];
 #pragma unroll
@@ -277,8 +306,8 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
         return ok ? stg + (size_t)(N2 * 4 * g + n2) * LS + unit * PPT + s1 : stg + PPB;
     };
 
-    static_for<0, F>([&](auto fc) {
-        constexpr int f = decltype(fc)::value;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
         __syncthreads();  // the previous field's tiles have been read
 #pragma unroll
         for (int k = 0; k < C::LMAX; ++k) {
@@ -286,14 +315,21 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
             if (it < nrun) {
                 const int zz = it / QPR, q = it % QPR;
                 unsigned *row = stg + (size_t)(a.z0 + zz) * LS + 4 * q;
-                row[0] = pre[k].x;
-                row[1] = pre[k].y;
-                row[2] = pre[k].z;
-                row[3] = pre[k].w;
+                row[0] = pre[k][0];
+                row[1] = pre[k][1];
+                row[2] = pre[k][2];
+                row[3] = pre[k][3];
             }
         }
+#pragma unroll
+        for (int k = 0; k < C::SMAX; ++k) {
+            const int it = tid + k * NT;
+            if (it < field_ncomp<KIND>(f) * PPB * C::SRUNS)
+                *reinterpret_cast<u32x4 *>(sspec + 8 * it) = spre[k];  // [slot][pencil][kz] in run order
+        }
         __syncthreads();
-        if constexpr (f + 1 < F) load_field(f + 1);  // in flight during the transforms
+        if (f + 1 < F)  // in flight during the transforms
+            z16_load_field<P, KIND>(f + 1, a, Y, spec, fstride, nrun, kx, ky0, pre, spre);
 #pragma unroll
         for (int u = 0; u < UPW; ++u) {
             const int unit = u * C::WAVES + wave;
@@ -336,21 +372,17 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const unsigned kd = kzo[(4 * t2 + r) * 64 + lane];
-                    const int ky = kyu + (PPT == 1 ? 0 : (int)((kd >> 16) & 0xffu));
-                    const bool fy = ky >= a.hy;
-                    const int kyp = fy ? a.py - ky : ky;
-                    const unsigned off = (unsigned)((kx * a.hy + kyp) * a.hz) + (kd & 0xffffu);
+                    const int pen = unit * PPT + (PPT == 1 ? 0 : (int)((kd >> 16) & 0xffu));
+                    const bool fy = ky0 + pen >= a.hy;
                     const unsigned zs = kd & kKzSign, ys = fy ? kKzSign : 0u;
+                    const uint16_t *srow = sspec + pen * C::HZS + (kd & 0xffffu);
                     const float xr = X[t2].re[r], xi = X[t2].im[r];
                     static_for<0, T::N>([&](auto tc) {
                         constexpr int term = decltype(tc)::value;
-                        if constexpr (T::f(term) == f) {
+                        if (T::f(term) == f) {
                             constexpr int comp = T::c(term);
                             constexpr int mask = comp_oddmask(KIND, comp);
-                            // uniform component base + 32-bit byte offset (spectra of one
-                            // component span less than 4 GB)
-                            const char *sc = reinterpret_cast<const char *>(spec + comp * cstride);
-                            unsigned bits = (unsigned)*reinterpret_cast<const uint16_t *>(sc + (off << 1)) << 16;
+                            unsigned bits = (unsigned)srow[term_slot<KIND>(term) * PPB * C::HZS] << 16;
                             if constexpr (mask & 4) bits ^= zs;
                             if constexpr (mask & 2) bits ^= ys;
                             const float sv = __uint_as_float(bits);
@@ -367,7 +399,7 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
                 }
             }
         }
-    });
+    }
 
     // inverse transforms, one output at a time through the staging tile
     unsigned *Z = static_cast<unsigned *>(a.Z) + (size_t)kx * a.nzo * a.py + ky0;
@@ -413,7 +445,12 @@ __device__ __forceinline__ void zpass16_body(const ApplyArgs &a, const int kx, c
         for (int it = tid; it < nrun; it += NT) {
             const int zz = it / QPR, q = it % QPR;
             const unsigned *row = stg + (size_t)(a.z0 + zz) * LS + 4 * q;
-            *reinterpret_cast<uint4 *>(Zo + (size_t)zz * a.py + 4 * q) = make_uint4(row[0], row[1], row[2], row[3]);
+            u32x4 v;
+            v[0] = row[0];
+            v[1] = row[1];
+            v[2] = row[2];
+            v[3] = row[3];
+            *reinterpret_cast<u32x4 *>(Zo + (size_t)zz * a.py + 4 * q) = v;
         }
     }
 }
@@ -432,8 +469,8 @@ __global__ __launch_bounds__(256) void k_zpass16(ApplyArgs a, int nby) {
 template <int P, int KIND>
 int launch_z16(const ApplyArgs &a, hipStream_t st) {
     using C = Z16Cfg<P, KIND>;
-    if (a.py % C::PPB != 0) {
-        set_error("16-bit z pass: y length not a multiple of the block's pencils");
+    if (a.py % C::PPB != 0 || a.hzs != C::HZS) {
+        set_error("16-bit z pass: y length not a multiple of the block's pencils, or unpadded spectra");
         return BEMFFT_EUNSUPPORTED;
     }
     const int nby = a.py / C::PPB;

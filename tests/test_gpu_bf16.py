@@ -114,8 +114,8 @@ def test_bf16_config3_navier_star_full_size(dev):
     err, info = _err(dev, g, B.NAVIER3D, targets=(2000, 2120))
     print(f"bf16 navier star192: {err:.2e}")
     assert info["pad"] == [384, 384, 384] and err < BAR
-    # the spectra are stored in 16 bits: half the FP32 bytes
-    assert info["spectra_bytes"] == 24 * 193 ** 3 * 2
+    # the spectra are stored in 16 bits, kz rows padded to 200 values
+    assert info["spectra_bytes"] == 24 * 193 * 193 * 200 * 2
 
 
 def test_bf16_refined_solves_reach_fp64(dev):
