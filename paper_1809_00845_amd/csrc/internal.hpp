@@ -107,6 +107,7 @@ struct bemfft_plan {
     double *s_red = nullptr;   // reduction scratch
     double *s_hbuf = nullptr;  // device copy of Hessenberg column / coefficients
     double *h_pinned = nullptr;
+    uint64_t s_seq = 0;        // last step number handed to a GMRES completion flag
 };
 
 namespace bemfft {

@@ -158,6 +158,165 @@ __global__ __launch_bounds__(256) void k_gemv_norm(const double *V, int64_t ld, 
     if (threadIdx.x == 0) partial[blockIdx.x] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
 }
 
+// ---- Arnoldi kernels that reduce the inner-product partials themselves.
+// Every block forms the same sums from the block partials in the fixed order
+// of k_mdot_final (lane-strided, then a fixed shuffle tree), so no separate
+// reduction launch sits between the partials and their consumer.
+constexpr int kRedPart = 128;   // blocks of the partial inner products
+constexpr int kConsumer = 128;  // blocks of the consumers (each re-reduces the partials)
+
+// h[j] = sum over the kRedPart block partials of column j: wave q of the
+// four sums partials 32 q .. 32 q + 31 of 64 columns at a time (sixteen
+// loads in flight at once), then the four are added in a fixed order.
+__device__ __forceinline__ void reduce_partials(const double *partial, int nvec, double *h) {
+    static_assert(kRedPart == 128, "four waves of thirty-two partials");
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    for (int j0 = 0; j0 < nvec; j0 += 64) {
+        const int j = j0 + lane;
+        double s = 0.0;
+#pragma unroll
+        for (int b0 = 0; b0 < 32; b0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) v[b] = j < nvec ? partial[(int64_t)(32 * wave + b0 + b) * nvec + j] : 0.0;
+#pragma unroll
+            for (int b = 0; b < 16; ++b) s += v[b];
+        }
+        part[wave][lane] = s;
+        __syncthreads();
+        if (wave == 0 && j < nvec) h[j] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        __syncthreads();
+    }
+}
+
+// h = sum of the partials of V^T w; block 0 writes h to hout; w += sign V h
+__global__ __launch_bounds__(256) void k_gemv_r(const double *V, int64_t ld, int nvec, const double *partial,
+                                                double *w, int64_t n, double sign, double *hout) {
+    __shared__ double h[512];
+    reduce_partials(partial, nvec, h);
+    if (blockIdx.x == 0) {  // hout may be pinned host memory
+        for (int j = threadIdx.x; j < nvec; j += blockDim.x) hout[j] = h[j];
+        __threadfence_system();
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int j = 0;
+        for (; j + 8 <= nvec; j += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        }
+        for (int k = 0; j + k < nvec; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        const double sm = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        w[i] += sign * sm;
+    }
+}
+
+// As k_gemv_r with sign -1, and each block's sum of the updated w[i]^2 into
+// pout[block]
+__global__ __launch_bounds__(256) void k_gemv_norm_r(const double *V, int64_t ld, int nvec, const double *partial,
+                                                     double *w, int64_t n, double *hout, double *pout) {
+    __shared__ double h[512];
+    __shared__ double sm4[4];
+    reduce_partials(partial, nvec, h);
+    if (blockIdx.x == 0) {  // hout may be pinned host memory
+        for (int j = threadIdx.x; j < nvec; j += blockDim.x) hout[j] = h[j];
+        __threadfence_system();
+    }
+    double ss = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int j = 0;
+        for (; j + 8 <= nvec; j += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        }
+        for (int k = 0; j + k < nvec; ++k) acc[k] += V[(int64_t)(j + k) * ld + i] * h[j + k];
+        const double sm = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        const double wi = w[i] - sm;
+        w[i] = wi;
+        ss += wi * wi;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    if (threadIdx.x % 64 == 0) sm4[threadIdx.x / 64] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) pout[blockIdx.x] = (sm4[0] + sm4[1]) + (sm4[2] + sm4[3]);
+}
+
+// ||w|| = sqrt(sum of the norm partials), then v = w / ||w|| stored as the
+// basis column and v * scale split into the unknown slots of (q, u); block
+// 0 writes ||w|| to nout if given
+__global__ __launch_bounds__(256) void k_split_norm_r(const uint8_t *bc, const double *w, const double *pnorm, int nblk,
+                                                      const double *scale, double *v_out, double *q, double *u,
+                                                      int64_t n, double *nout) {
+    __shared__ double nrm[1];
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 64) s += pnorm[b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) nrm[0] = sqrt(s);
+    }
+    __syncthreads();
+    const double a = nrm[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nout) {  // pinned host memory
+        *nout = a;
+        __threadfence_system();
+    }
+    const double inv = a > 0.0 ? 1.0 / a : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = w[i] * inv;
+        v_out[i] = v;
+        const double vs = v * scale[i];
+        const bool qslot = bc[i] == 0;  // unknown: q where u is known
+        q[i] = qslot ? vs : 0.0;
+        u[i] = qslot ? 0.0 : vs;
+    }
+}
+
+// out = sqrt(sum of the norm partials) (same order as k_split_norm_r); then,
+// if flag is given (pinned host memory), the step's sequence number is
+// stored there with system-scope release: everything the step wrote for the
+// host is visible once the host reads it
+__global__ __launch_bounds__(64) void k_norm_r(const double *pnorm, int nblk, double *out, uint64_t *flag,
+                                               uint64_t seq) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 64) s += pnorm[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) {  // out may be pinned host memory
+        *out = sqrt(s);
+        __threadfence_system();
+        if (flag) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Host side: wait until the device has stored seq at flag (pinned memory).
+// Spins (the answer comes within one step of the solve); checks the stream
+// for errors every few milliseconds and gives up after 120 s.
+int wait_step_flag(const uint64_t *flag, uint64_t seq, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t spins = 1;; ++spins) {
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return 0;
+        if ((spins & 0x3fff) == 0) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q != hipSuccess && q != hipErrorNotReady) {
+                set_error(std::string("GMRES: stream error while waiting: ") + hipGetErrorString(q));
+                return BEMFFT_EDEVICE;
+            }
+            if (q == hipSuccess && __atomic_load_n(flag, __ATOMIC_ACQUIRE) != seq) {
+                set_error("GMRES: the stream drained without the step's completion flag");
+                return BEMFFT_EDEVICE;
+            }
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120)) {
+                set_error("GMRES: timed out waiting for a step");
+                return BEMFFT_EDEVICE;
+            }
+        }
+    }
+}
+
 // v = w / norm, norm read from device memory
 __global__ void k_normalize(const double *w, const double *norm, double *v, int64_t n) {
     double a = *norm;
@@ -252,23 +411,16 @@ double norm2(const double *v, int64_t n, Ws &ws, double *pinned, hipStream_t st,
 // residual tolerance tol, at most maxit iterations.  Uses ws.w, ws.r, ws.q,
 // ws.u, ws.V.  Returns the status; iters and the final true relative
 // residual (w.r.t. ||rhs||) through the pointers.
-// pipelined = false (the allocation-free entry point): no events are created
-// and each step is waited for with a stream synchronisation before the next
-// one is queued (hp may then be ordinary pageable host memory).
+// pipelined = true: hp is pinned host memory that the step kernels write
+// into, and the host polls each step's completion flag there.  pipelined =
+// false (the allocation-free entry point): each step is waited for with a
+// stream synchronisation before the next one is queued and its column is
+// copied (hp may then be ordinary pageable host memory).
 int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double *rhs, double *x, bool x_zero,
                double tol, int mcap, int maxit, Ws &ws, double *hp, hipStream_t st, int *iters_out, int *restarts_out,
                double *relres_out, const double *r0_given, bool pipelined) {
     const int64_t n = (int64_t)p->ncomp * p->m;
     int status = 0;
-    struct Events {
-        hipEvent_t e[2] = {nullptr, nullptr};
-        ~Events() {
-            for (hipEvent_t x : e)
-                if (x) (void)hipEventDestroy(x);
-        }
-    } evs;
-    if (pipelined)
-        for (hipEvent_t &x : evs.e) BF_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
     const double bnorm = norm2(rhs, n, ws, hp, st, &status);
     BF_CHECK(status);
     int iters = 0, cycles = 0;
@@ -316,31 +468,44 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         // Step kk is queued one step ahead: step k + 1 goes to the GPU before
         // the host waits for step k's Hessenberg column (its inputs are all on
         // the device), so the GPU keeps working while the host applies the
-        // rotations.  Each step copies its column to its own half of the
-        // pinned buffer; a step queued past convergence only fills scratch.
+        // rotations.  The column of step kk -- h1 at [0, kk], h2 at [512,
+        // 512 + kk], ||w|| at 512 + kk + 1 -- is written by the kernels
+        // themselves into half kk & 1 of the pinned host buffer (unpipelined:
+        // into the device buffer, copied after the step).  The next step's
+        // first kernel reduces ||w|| again from the same partials, in the same
+        // order, to normalise w.  A step queued past convergence only fills
+        // scratch.
+        double *red1 = ws.red, *red2 = ws.red + 65536, *red3 = ws.red + 131072 - 256;
+        // completion flags carry a number never used before on this plan
+        const uint64_t seq0 = p->s_seq;
+        p->s_seq += (uint64_t)mcap + 1;
+        auto step_seq = [&](int kk) { return seq0 + (uint64_t)kk + 1; };
+        const int gc = std::min(kConsumer, grid_for(n));
+        auto col_of = [&](int kk) { return pipelined ? hp + 1024 * (kk & 1) : ws.hd; };
         auto queue_step = [&](int kk) -> int {
             double *vk = ws.V + (int64_t)kk * n;
-            double *h1 = ws.hd, *h2 = ws.hd + 512;
-            // w = A Dinv v_k; for k > 0, v_k = w / ||w|| of the previous step is
-            // formed in the same pass that splits it into the apply's slots
+            double *hc = col_of(kk);
+            // w = A Dinv v_k; for k > 0, v_k = w / ||w|| of the previous step
             if (kk == 0) {
                 BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
             } else {
-                hipLaunchKernelGGL(k_split_norm, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, h2 + kk, ws.dinv, vk,
-                                   ws.q, ws.u, n);
+                hipLaunchKernelGGL(k_split_norm_r, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, red3, gc, ws.dinv, vk,
+                                   ws.q, ws.u, n, (double *)nullptr);
                 BF_HIP(hipGetLastError());
                 BF_CHECK(launch_apply(p, e, ws.q, ws.u, ws.w, st));
             }
             // classical Gram-Schmidt, twice; the second update also sums ||w||^2
-            BF_CHECK(mdot(ws.V, n, kk + 1, ws.w, n, ws.red, h1, 0, st));
-            hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, kk + 1, h1, ws.w, n, -1.0);
-            BF_CHECK(mdot(ws.V, n, kk + 1, ws.w, n, ws.red, h2, 0, st));
-            const int gn = grid_for(n);
-            hipLaunchKernelGGL(k_gemv_norm, dim3(gn), dim3(256), 0, st, ws.V, n, kk + 1, h2, ws.w, n, ws.red);
-            hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(64), 0, st, ws.red, gn, 1, h2 + kk + 1, 1);
+            hipLaunchKernelGGL(k_mdot_partial, dim3(kRedPart, (kk + 1 + 7) / 8), dim3(kRedThreads), 0, st, ws.V, n, kk + 1,
+                               ws.w, n, red1);
+            hipLaunchKernelGGL(k_gemv_r, dim3(gc), dim3(256), 0, st, ws.V, n, kk + 1, red1, ws.w, n, -1.0, hc);
+            hipLaunchKernelGGL(k_mdot_partial, dim3(kRedPart, (kk + 1 + 7) / 8), dim3(kRedThreads), 0, st, ws.V, n, kk + 1,
+                               ws.w, n, red2);
+            hipLaunchKernelGGL(k_gemv_norm_r, dim3(gc), dim3(256), 0, st, ws.V, n, kk + 1, red2, ws.w, n, hc + 512,
+                               red3);
+            uint64_t *flag = pipelined ? reinterpret_cast<uint64_t *>(hc + 1023) : nullptr;
+            hipLaunchKernelGGL(k_norm_r, dim3(1), dim3(64), 0, st, red3, gc, hc + 512 + kk + 1, flag, step_seq(kk));
             BF_HIP(hipGetLastError());
-            BF_HIP(hipMemcpyAsync(hp + 1024 * (kk & 1), ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
-            if (pipelined) BF_HIP(hipEventRecord(evs.e[kk & 1], st));
+            if (!pipelined) BF_HIP(hipMemcpyAsync(hp, ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
             return 0;
         };
         const int kmax = std::min(mcap, maxit - iters);
@@ -348,12 +513,12 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         for (; k < kmax; ++k) {
             if (pipelined) {
                 if (k + 1 < kmax) BF_CHECK(queue_step(k + 1));
-                BF_HIP(hipEventSynchronize(evs.e[k & 1]));
+                BF_CHECK(wait_step_flag(reinterpret_cast<const uint64_t *>(col_of(k) + 1023), step_seq(k), st));
             } else {
                 BF_CHECK(queue_step(k));
                 BF_HIP(hipStreamSynchronize(st));
             }
-            const double *hk = hp + 1024 * (k & 1);
+            const double *hk = pipelined ? col_of(k) : hp;
             ++iters;
             double *col = &H[(size_t)k * (mcap + 1)];
             for (int i = 0; i <= k; ++i) col[i] = hk[i] + hk[512 + i];
