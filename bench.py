@@ -30,19 +30,51 @@ METRIC = "BEM matvecs/s + GMRES time-to-solve @1e-6 rel. residual; HBM roofline 
 HBM_PEAK_GBS = 8000.0
 
 
-def stage_bytes(info, prec_bytes):
-    """Algorithmic HBM bytes of each stage for one apply (the bytes each
-    kernel must read or write once; node data O(M) included)."""
+def model_bytes(info, b):
+    """The byte model of one apply (b = bytes per stored real): per field
+    f = Hx Ny Nz 2b (the x-pass half spectrum), g = Hx Py Nz 2b (after the
+    y pass); forward x, y: F (2f + g); fused z pass with the products:
+    F g + K Hx Hy Hz b + O g; inverse y, x: O (g + 2f).  It credits the
+    zero padding, the half spectrum, the octant spectra and the fused scatter
+    and gather, not the occupancy of the boundary."""
+    px, py, pz = info["pad"]
+    hx, hy, hz = px // 2 + 1, py // 2 + 1, pz // 2 + 1
+    ny, nz = info["n"][1], info["n"][2]
+    F, K, O = info["nfields"], info["nspectra"], info["noutputs"]
+    f = hx * ny * nz * 2 * b
+    g = hx * py * nz * 2 * b
+    return {"forward_xy": F * (2 * f + g), "zpass": F * g + K * hx * hy * hz * b + O * g,
+            "inverse_yx": O * (g + 2 * f)}
+
+
+def zpass_roofline(info, b, ms, kernel):
+    """Roofline object of the z pass: the model's bytes (model_bytes) over
+    its measured time, and the bytes the design must move (occupied planes
+    only) beside it."""
+    mb = model_bytes(info, b)["zpass"]
+    moved = stage_bytes(info, b)["zpass"]
+    gbs = mb / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "model_bytes": mb, "ms": ms,
+            "occupied_planes_bytes": moved, "frac_occupied_planes_bytes": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def stage_bytes(info, prec_bytes, arith_bytes=None):
+    """Bytes of each stage of this design for one apply (the bytes each
+    kernel must read or write once, occupied planes only; node data O(M)
+    included).  prec_bytes: stored real (Y, Z, spectra); arith_bytes: real
+    of the inverse-y rows and the node fields (default prec_bytes)."""
+    ab = arith_bytes or prec_bytes
     px, py, pz = info["pad"]
     hx, hy, hz = px // 2 + 1, py // 2 + 1, pz // 2 + 1
     nzo = info["z_count"]
     F, K, O, m = info["nfields"], info["nspectra"], info["noutputs"], info["m"]
     cb = 2 * prec_bytes
     g = hx * nzo * py * cb                     # one complex field after the y transform
-    spec = K * hx * hy * hz * prec_bytes       # octant spectra
+    spec = info["spectra_bytes"]               # octant spectra as stored
     nodes_in = m * (8 * 2 * info["ncomp"] + 4 * 4 + 8 * 4)
     ny = info["n"][1]
-    w = O * hx * ny * nzo * cb                 # inverse-y rows y < ny, kx contiguous
+    w = O * hx * ny * nzo * 2 * ab             # inverse-y rows y < ny, kx contiguous
     return {
         "fwd_xy": F * g + nodes_in,
         "zpass": F * g + spec + O * g,
@@ -181,6 +213,22 @@ def bench_halfspace(B, I, dev, steps):
     return out
 
 
+def median_apply_ms(plan, q, u, r, n=100):
+    """Median of n single applies, each bracketed by HIP events on the
+    stream the apply is queued on."""
+    import torch
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for _ in range(5):
+        plan.apply(q, u, r)
+    for a, b in evs:
+        a.record()
+        plan.apply(q, u, r)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
 def timed_applies(plan, q, u, r, steps, warmup):
     import torch
 
@@ -315,8 +363,10 @@ def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
 
 def bench_navier_star(B, I, dev, steps):
     """Navier (Kelvin, nu = 0.3, mu = 1) on the star surface of seed 1 on a
-    192^3 grid padded to 384^3: FP32 / FP64 applies and time to solve for the
-    traction under a given linear displacement field, to 1e-6."""
+    192^3 grid padded to 384^3: FP32, FP64 and 16-bit (BF16 storage, z
+    transforms on the matrix cores) applies with the z pass against the HBM
+    roofline, and time to solve for the traction under a given linear
+    displacement field, to 1e-6 (plan + solve and solve alone)."""
     import torch
 
     t0 = time.perf_counter()
@@ -327,31 +377,77 @@ def bench_navier_star(B, I, dev, steps):
     u = torch.tensor(rng.uniform(-1, 1, (3, g.m)), device=dev)
     r = torch.empty_like(u)
     out = {"nodes": g.m, "grid": 192, "pad": 384, "voxelise_s": t_geom}
-    p32 = B.Plan(g, B.NAVIER3D, precision=B.FP32, nu=0.3, mu=1.0, keep_fp64=True, autotune=1)
-    p64 = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=0.3, mu=1.0, autotune=1)
-    n32, n64 = max(20, steps // 4), max(10, steps // 10)
-    out["fp32_matvec_s"] = n32 / timed_applies(p32, q, u, r, n32, 5)
-    out["fp64_matvec_s"] = n64 / timed_applies(p64, q, u, r, n64, 3)
     names = ["fwd_xy", "zpass", "inv_y", "gather"]
-    out["fp32_stage_ms"] = dict(zip(names, B.bemfft_apply_profile(p32.handle, q, u, r, reps=20)))
-    out["plan_seconds"] = {"fp32_keep_fp64": p32.info()["plan_seconds"], "fp64": p64.info()["plan_seconds"]}
+    plans = {}
+    for tag, prec, b in (("fp32", B.FP32, 4), ("fp64", B.FP64, 8), ("bf16_mfma", B.BF16_MFMA, 2)):
+        pl = B.Plan(g, B.NAVIER3D, precision=prec, nu=0.3, mu=1.0, keep_fp64=prec != B.FP64,
+                    autotune=1 if prec != B.BF16_MFMA else 0)
+        plans[tag] = pl
+        inf = pl.info()
+        n = max(10, steps // (10 if prec == B.FP64 else 4))
+        st = B.bemfft_apply_profile(pl.handle, q, u, r, reps=20)
+        kern = "k_zpass16" if prec == B.BF16_MFMA else "k_zpass"
+        out[tag] = {"matvec_s": n / timed_applies(pl, q, u, r, n, 3),
+                    "apply_ms_median": median_apply_ms(pl, q, u, r, 50),
+                    "stage_ms": dict(zip(names, st)),
+                    "plan_seconds": inf["plan_seconds"],
+                    "roofline": zpass_roofline(inf, b, st[1], kern),
+                    "apply_model_bytes": sum(model_bytes(inf, b).values())}
+    out["roofline"] = out["fp32"]["roofline"]
     E = np.random.default_rng(11).normal(size=(3, 3))
     uu = (g.rel() @ E.T).T
     bct = torch.zeros((3, g.m), dtype=torch.uint8, device=dev)
     known = torch.tensor(np.ascontiguousarray(uu), device=dev)
     solves = {}
-    for tag, pl, kw in (("fp64", p64, {}), ("fp32", p32, {}), ("fp32_refined_fp64", p32, {"refine": 1, "inner_tol": 1e-3})):
+    for tag, pl, kw in (("fp64", plans["fp64"], {}), ("fp32", plans["fp32"], {}),
+                        ("fp32_refined_fp64", plans["fp32"], {"refine": 1, "inner_tol": 1e-3}),
+                        ("bf16_mfma_refined_fp64", plans["bf16_mfma"], {"refine": 1, "inner_tol": 1e-2})):
         pl.solve(bct, known, tol=1e-6, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, si = pl.solve(bct, known, tol=1e-6, **kw)
         torch.cuda.synchronize()
-        solves[tag] = {"seconds": time.perf_counter() - t0, "iters": si["iters"], "outer": si["outer"],
-                       "true_relres": si["true_relres"], "status": si["status"],
+        dt = time.perf_counter() - t0
+        solves[tag] = {"seconds": dt, "plan_plus_solve_s": dt + pl.info()["plan_seconds"], "iters": si["iters"],
+                       "outer": si["outer"], "true_relres": si["true_relres"], "status": si["status"],
                        "residual_precision": "fp32" if tag == "fp32" else "fp64"}
     out["time_to_solve_1e-6"] = solves
-    p32.close()
-    p64.close()
+    for pl in plans.values():
+        pl.close()
+    return out
+
+
+def bench_cube_bf16(B, I, dev, cube, q, u, steps):
+    """The 16-bit form on the headline cube: applies (z pass on the matrix
+    cores) with its roofline, and mixed-problem solves to 1e-6 with FP64
+    refinement."""
+    import torch
+
+    r = torch.empty_like(u)
+    pl = B.Plan(cube, B.LAPLACE3D, precision=B.BF16_MFMA, keep_fp64=True)
+    inf = pl.info()
+    names = ["fwd_xy", "zpass", "inv_y", "gather"]
+    st = B.bemfft_apply_profile(pl.handle, q, u, r, reps=max(20, steps // 4))
+    out = {"matvec_s": steps / timed_applies(pl, q, u, r, steps, 5),
+           "apply_ms_median": median_apply_ms(pl, q, u, r, 100),
+           "stage_ms": dict(zip(names, st)),
+           "roofline": zpass_roofline(inf, 2, st[1], "k_zpass16"),
+           "apply_model_bytes": sum(model_bytes(inf, 2).values()),
+           "plan_seconds": inf["plan_seconds"]}
+    uu, qq = I.harmonic_3d_xyz(cube)
+    bc = I.mixed_bc_upper(cube)
+    known = torch.tensor(np.where(bc == 0, uu, qq), device=dev)
+    bct = torch.tensor(bc, device=dev)
+    pl.solve(bct, known, tol=1e-6, refine=1, inner_tol=1e-2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, si = pl.solve(bct, known, tol=1e-6, refine=1, inner_tol=1e-2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["refined_solve_1e-6"] = {"seconds": dt, "plan_plus_solve_s": dt + inf["plan_seconds"],
+                                 "iters": si["iters"], "outer": si["outer"], "true_relres": si["true_relres"],
+                                 "status": si["status"], "residual_precision": "fp64"}
+    pl.close()
     return out
 
 
@@ -440,6 +536,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-shape batched workload")
     ap.add_argument("--batched-only", action="store_true", help="only the 64-shape batched workload")
     ap.add_argument("--no-navier", action="store_true", help="skip the 192^3 Navier star workload")
+    ap.add_argument("--navier-only", action="store_true", help="only the 192^3 Navier star workload (for profilers)")
+    ap.add_argument("--bf16-only", action="store_true",
+                    help="only the 16-bit cube applies (z pass on the matrix cores; for profilers)")
     ap.add_argument("--solve-only", action="store_true",
                     help="only the mixed cube solves to 1e-6 (FP64 and FP32 plans), 3 each (for profilers)")
     ap.add_argument("--halfspace-only", action="store_true",
@@ -490,6 +589,9 @@ def main():
     if args.cg_only:
         print(json.dumps(bench_dirichlet_cg(B, I, dev)), flush=True)
         return
+    if args.navier_only:
+        print(json.dumps(bench_navier_star(B, I, dev, args.steps)), flush=True)
+        return
     if args.solve_only:
         g = I.cube3d(128, 100)
         uu, qq = I.harmonic_3d_xyz(g)
@@ -518,6 +620,11 @@ def main():
     u = torch.tensor(un, device=dev)
     r = torch.empty_like(u)
 
+    if args.bf16_only:
+        pl = B.Plan(cube, B.LAPLACE3D, precision=B.BF16_MFMA)
+        dt = timed_applies(pl, q, u, r, args.steps, args.warmup)
+        print(json.dumps({"workload": "laplace3d cube 128^3 16-bit applies", "matvec_s": args.steps / dt}), flush=True)
+        return
     plan = B.Plan(cube, B.LAPLACE3D, precision=B.FP32, keep_fp64=True, autotune=1)
     info = plan.info()
     if args.grid_eval_only:
@@ -532,6 +639,8 @@ def main():
     stages = {n: {"ms": ms, "gbs": sb[n] / (ms * 1e-3) / 1e9, "bytes": sb[n]} for n, ms in zip(names, stage_ms)}
     dom = max(names, key=lambda n: stages[n]["ms"])
     apply_bytes = sum(sb.values())
+    model = model_bytes(info, 4)
+    zroof = zpass_roofline(info, 4, stages["zpass"]["ms"], "k_zpass")
     workload = "laplace3d_cube_surface_128cubed_pad256_fp32"
     out = {
         "metric": METRIC,
@@ -549,11 +658,17 @@ def main():
         "config": {"workload": workload, "nodes": cube.m, "grid": 128,
                    "pad": 256, "edge_points": 100, "occupied_planes": info["z_count"],
                    "z_schedule": info["zsched"], "autotune_us": info["tune_us"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": stages[dom]["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": stages[dom]["gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(workload, dom)},
+        # the dominant kernel is the z pass; achieved = the model's z-pass bytes
+        # (F g + K Hx Hy Hz b + O g) over its mean event time
+        "roofline": {"bound": "hbm", "kernel": "k_zpass", "achieved": zroof["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": zroof["frac"], "traffic": measured_traffic(workload, "zpass"),
+                     "model_bytes": zroof["model_bytes"],
+                     "frac_occupied_planes_bytes": zroof["frac_occupied_planes_bytes"]},
+        "apply_ms_median": median_apply_ms(plan, q, u, r, max(50, args.steps // 2)),
         "stages": stages,
         "apply_gbs": apply_bytes / (sum(stage_ms) * 1e-3) / 1e9,
+        "apply_model_bytes": sum(model.values()),
+        "apply_model_frac": sum(model.values()) / (sum(stage_ms) * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "zpass_alu_view": zpass_alu_view(info, stages["zpass"]["ms"]),
     }
     if not args.quick:
@@ -593,7 +708,9 @@ def main():
                 t0 = time.perf_counter()
                 x, si = pl.solve(bct, known, tol=1e-6, **kw)
                 torch.cuda.synchronize()
-                solves[f"{name}_{tag}"] = {"seconds": time.perf_counter() - t0, "iters": si["iters"],
+                dts = time.perf_counter() - t0
+                solves[f"{name}_{tag}"] = {"seconds": dts, "plan_plus_solve_s": dts + pl.info()["plan_seconds"],
+                                           "iters": si["iters"],
                                            "outer": si["outer"], "true_relres": si["true_relres"],
                                            "residual_precision": "fp64" if tag != "fp32" else "fp32",
                                            "status": si["status"]}
@@ -601,6 +718,7 @@ def main():
         extra["dirichlet_cg_vs_gmres"] = bench_dirichlet_cg(B, I, dev)
         extra["halfspace_256sq"] = bench_halfspace(B, I, dev, max(20, args.steps // 4))
         extra["plan_seconds_cube_fp32"] = info["plan_seconds"]
+        extra["cube_bf16_mfma"] = bench_cube_bf16(B, I, dev, cube, q, u, args.steps)
         if not args.no_navier:
             print("  navier star 192^3 ...", file=sys.stderr, flush=True)
             extra["navier_star_192"] = bench_navier_star(B, I, dev, args.steps)
