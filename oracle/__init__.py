@@ -71,11 +71,12 @@ def lib():
         L.orc_snap.restype = ctypes.c_long
         L.orc_apply.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_long, lp, dp, dp, ctypes.c_int, dp, dp, dp,
-                                ctypes.c_long, ctypes.c_long, dp, dp, dp]
+                                ctypes.c_long, ctypes.c_long, dp, dp, dp, ctypes.c_int, dp, dp]
         L.orc_assemble.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_long, lp, dp, dp, dp, dp, dp]
+                                   ctypes.c_long, lp, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp]
         L.orc_volume.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_long, lp, dp, dp, dp, dp, ctypes.c_long, lp, dp, dp]
+                                 ctypes.c_long, lp, dp, dp, dp, dp, ctypes.c_long, lp, dp, dp,
+                                 ctypes.c_int, dp, dp]
         L.orc_halfspace.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_self_halfspace.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_num_threads.restype = ctypes.c_int
@@ -182,6 +183,7 @@ class Problem:
     weights: np.ndarray
     nu: float = 0.3
     mu: float = 1.0
+    cell_quad: int = 0  # 0: kernels point-sampled at offsets m != 0; q >= 2: cell means
 
     @property
     def dim(self):
@@ -196,7 +198,7 @@ class Problem:
         return int(self.weights.shape[0])
 
 
-def problem(geom, kernel, nu=0.3, mu=1.0) -> Problem:
+def problem(geom, kernel, nu=0.3, mu=1.0, cell_quad=0) -> Problem:
     """Build an oracle Problem from any object with dim/n/h/origin/nodes/
     normals/weights attributes (the shared input generators make those)."""
     d = geom.dim
@@ -204,7 +206,22 @@ def problem(geom, kernel, nu=0.3, mu=1.0) -> Problem:
                    np.asarray(geom.n[:d], dtype=np.int64),
                    np.ascontiguousarray(geom.nodes, dtype=np.float64),
                    np.ascontiguousarray(geom.normals, dtype=np.float64),
-                   np.ascontiguousarray(geom.weights, dtype=np.float64), nu, mu)
+                   np.ascontiguousarray(geom.weights, dtype=np.float64), nu, mu, int(cell_quad))
+
+
+def cell_rule(q: int):
+    """The per-axis rule of the cell means (constant elements, Sec. 4 /
+    Fig. 5): q Gauss-Legendre points on [-1/2, 1/2] (numpy's ``leggauss``,
+    rescaled) with weights summing to 1.  q = 0: point values."""
+    if q <= 0:
+        return np.zeros(1), np.zeros(1)
+    x, w = np.polynomial.legendre.leggauss(int(q))
+    return np.ascontiguousarray(0.5 * x), np.ascontiguousarray(0.5 * w)
+
+
+def _rule_args(p: Problem):
+    x, w = cell_rule(p.cell_quad)
+    return (int(max(p.cell_quad, 0)), x, w)
 
 
 def snap(p: Problem) -> np.ndarray:
@@ -235,8 +252,9 @@ def apply(p: Problem, q, u, cmode=C_IMPLICIT, cuser=None, targets=None, with_sca
     else:
         cu = None
         cptr = None
+    cq, cx, cw = _rule_args(p)
     lib().orc_apply(p.kernel, p.nu, p.mu, p.h, p.m, _l(g), _d(p.normals), _d(p.weights), cmode,
-                    cptr, _d(q), _d(u), t0, t1, _d(r), _d(sc), _d(cbuf))
+                    cptr, _d(q), _d(u), t0, t1, _d(r), _d(sc), _d(cbuf), cq, _d(cx), _d(cw))
     out = [r if nc > 1 else r[0]]
     if with_scale:
         out.append(sc if nc > 1 else sc[0])
@@ -257,8 +275,9 @@ def volume(p: Problem, q, u, pts, with_scale=False):
     pts = np.ascontiguousarray(np.reshape(pts, (-1, p.dim)), dtype=np.int64)
     out = np.zeros((nc, pts.shape[0]))
     sc = np.zeros((nc, pts.shape[0]))
+    cq, cx, cw = _rule_args(p)
     lib().orc_volume(p.kernel, p.nu, p.mu, p.h, p.m, _l(g), _d(p.normals), _d(p.weights), _d(q), _d(u),
-                     pts.shape[0], _l(pts), _d(out), _d(sc))
+                     pts.shape[0], _l(pts), _d(out), _d(sc), cq, _d(cx), _d(cw))
     if nc == 1:
         out, sc = out[0], sc[0]
     return (out, sc) if with_scale else out
@@ -271,8 +290,9 @@ def assemble(p: Problem):
     S = np.zeros((n, n))
     D = np.zeros((n, n))
     c = np.zeros((p.m, p.ncomp * p.ncomp))
+    cq, cx, cw = _rule_args(p)
     lib().orc_assemble(p.kernel, p.nu, p.mu, p.h, p.m, _l(g), _d(p.normals), _d(p.weights),
-                       _d(S), _d(D), _d(c))
+                       _d(S), _d(D), _d(c), cq, _d(cx), _d(cw))
     return S, D, c
 
 

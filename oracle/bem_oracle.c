@@ -33,6 +33,12 @@
  *   - k != j but g_k == g_j (two nodes in one cell): the single layer uses the
  *     grid's value at offset 0, the flat-panel integral for the reference
  *     measure h^(d-1) divided by that measure (Navier: orientation average).
+ *   - kernel values at offsets m != 0: the kernel at the offset itself, or,
+ *     with a cell rule, its mean over the grid cell centred on the offset
+ *     (the constant-element reading of Sec. 4 / Fig. 5, taken literally);
+ *     the rule is a tensor product of q given points per axis on
+ *     [-1/2, 1/2] with weights summing to 1 (the callers pass Gauss-Legendre
+ *     points).  Offset 0 keeps the values above.
  *   - c_j: 1/2 (smooth boundary, eq. 4), user supplied, or implicit
  *     c_j = -D[1]_j (Navier: C_j = -[D e_1, D e_2, D e_3]_j), the rigid-mode
  *     identity of eq. (4)/(8) applied to the discrete operator.
@@ -274,6 +280,50 @@ static void double_block(int kernel, double nu, const double *xi, int same_cell,
     }
 }
 
+/* Cell rule for the kernel values at offsets m != 0 (see the header): q
+ * points x[] per axis on [-1/2, 1/2] with weights w[]; q = 0 samples the
+ * kernel at the offset itself. */
+typedef struct {
+    int q;
+    const double *x;
+    const double *w;
+} cell_rule;
+
+static int ncomp_of(int kernel);
+static int dim_of(int kernel);
+
+/* G and H of one pair: the point value at offset 0 and without a rule,
+ * else the weighted sum over the q^dim points of the cell around xi. */
+static void pair_blocks(int kernel, double nu, double mu, double h, const double *xi, int same_cell,
+                        int same_node, double wk, const double *nk, const cell_rule *cr, double G[9],
+                        double H[9])
+{
+    if (same_cell || cr->q <= 0) {
+        single_block(kernel, nu, mu, h, xi, same_cell, same_node, wk, nk, G);
+        double_block(kernel, nu, xi, same_cell, wk, nk, H);
+        return;
+    }
+    int dim = dim_of(kernel);
+    int nc = ncomp_of(kernel);
+    int q = cr->q;
+    for (int i = 0; i < nc * nc; ++i) G[i] = H[i] = 0.0;
+    int qz = (dim == 3) ? q : 1;
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b)
+            for (int c = 0; c < qz; ++c) {
+                double wt = cr->w[a] * cr->w[b] * (dim == 3 ? cr->w[c] : 1.0);
+                double pt[3] = {xi[0] + h * cr->x[a], xi[1] + h * cr->x[b],
+                                dim == 3 ? xi[2] + h * cr->x[c] : 0.0};
+                double g[9], hh[9];
+                single_block(kernel, nu, mu, h, pt, 0, 0, wk, nk, g);
+                double_block(kernel, nu, pt, 0, wk, nk, hh);
+                for (int i = 0; i < nc * nc; ++i) {
+                    G[i] += wt * g[i];
+                    H[i] += wt * hh[i];
+                }
+            }
+}
+
 static int ncomp_of(int kernel) { return (kernel == ORC_NAVIER3D || kernel == ORC_HALFSPACE) ? 3 : 1; }
 static int dim_of(int kernel) { return (kernel == ORC_LAPLACE2D || kernel == ORC_HALFSPACE) ? 2 : 3; }
 
@@ -289,13 +339,15 @@ static int dim_of(int kernel) { return (kernel == ORC_LAPLACE2D || kernel == ORC
  * scale[k][j] = |c u|_k + sum |D||u| + sum |S||q|, the magnitude of the terms
  * that cancel in r, used for normwise tolerances.
  * grid_index: [m][dim] snapped grid indices (from orc_snap).
+ * cq, cx, cw: the cell rule (cq = 0: point values; cx, cw unused).
  * Returns 0.
  */
 int orc_apply(int kernel, double nu, double mu, double h, long m, const long *grid_index,
               const double *normals, const double *weights, int cmode, const double *cuser,
               const double *q, const double *u, long t0, long t1, double *r, double *scale,
-              double *c_out)
+              double *c_out, int cq, const double *cx, const double *cw)
 {
+    cell_rule cr = {cq, cx, cw};
     int dim = dim_of(kernel);
     int nc = ncomp_of(kernel);
     long nt = t1 - t0;
@@ -314,8 +366,7 @@ int orc_apply(int kernel, double nu, double mu, double h, long m, const long *gr
                 if (d != 0) same_cell = 0;
             }
             double G[9], H[9];
-            single_block(kernel, nu, mu, h, xi, same_cell, k == j, weights[k], normals + k * dim, G);
-            double_block(kernel, nu, xi, same_cell, weights[k], normals + k * dim, H);
+            pair_blocks(kernel, nu, mu, h, xi, same_cell, k == j, weights[k], normals + k * dim, &cr, G, H);
             for (int a = 0; a < nc; ++a)
                 for (int b = 0; b < nc; ++b) {
                     double uk = u[b * m + k], qk = q[b * m + k];
@@ -365,8 +416,10 @@ int orc_apply(int kernel, double nu, double mu, double h, long m, const long *gr
  */
 int orc_volume(int kernel, double nu, double mu, double h, long m, const long *grid_index,
                const double *normals, const double *weights, const double *q, const double *u,
-               long npts, const long *pts, double *out, double *scale)
+               long npts, const long *pts, double *out, double *scale, int cq, const double *cx,
+               const double *cw)
 {
+    cell_rule cr = {cq, cx, cw};
     int dim = dim_of(kernel);
     int nc = ncomp_of(kernel);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -383,8 +436,7 @@ int orc_volume(int kernel, double nu, double mu, double h, long m, const long *g
                 if (d != 0) same_cell = 0;
             }
             double G[9], H[9];
-            single_block(kernel, nu, mu, h, xi, same_cell, 0, weights[k], normals + k * dim, G);
-            double_block(kernel, nu, xi, same_cell, weights[k], normals + k * dim, H);
+            pair_blocks(kernel, nu, mu, h, xi, same_cell, 0, weights[k], normals + k * dim, &cr, G, H);
             for (int a = 0; a < nc; ++a)
                 for (int b = 0; b < nc; ++b) {
                     acc[a] += G[a * nc + b] * q[b * m + k] - H[a * nc + b] * u[b * m + k];
@@ -406,8 +458,10 @@ int orc_volume(int kernel, double nu, double mu, double h, long m, const long *g
  * c_out as m * nc * nc blocks.
  */
 int orc_assemble(int kernel, double nu, double mu, double h, long m, const long *grid_index,
-                 const double *normals, const double *weights, double *S, double *D, double *c_implicit)
+                 const double *normals, const double *weights, double *S, double *D, double *c_implicit,
+                 int cq, const double *cx, const double *cw)
 {
+    cell_rule cr = {cq, cx, cw};
     int dim = dim_of(kernel);
     int nc = ncomp_of(kernel);
     long ld = nc * m;
@@ -425,8 +479,7 @@ int orc_assemble(int kernel, double nu, double mu, double h, long m, const long 
                 if (d != 0) same_cell = 0;
             }
             double G[9], H[9];
-            single_block(kernel, nu, mu, h, xi, same_cell, k == j, weights[k], normals + k * dim, G);
-            double_block(kernel, nu, xi, same_cell, weights[k], normals + k * dim, H);
+            pair_blocks(kernel, nu, mu, h, xi, same_cell, k == j, weights[k], normals + k * dim, &cr, G, H);
             for (int a = 0; a < nc; ++a)
                 for (int b = 0; b < nc; ++b) {
                     S[(a * m + j) * ld + b * m + k] = G[a * nc + b];
