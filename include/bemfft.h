@@ -130,6 +130,17 @@ typedef struct {
                                    (cached per kernel/precision/padded size
                                    in the file named by BEMFFT_TUNE_CACHE, if
                                    set), 2 the alternative one              */
+    int cell_quad;              /* kernel values at grid offsets m != 0
+                                   (Sec. 4 / Fig. 5 discretises the kernels
+                                   as constants per element): 0 or 1 the
+                                   kernel at the offset itself (default);
+                                   2..8 its mean over the grid cell of side h
+                                   centred on the offset, by a tensor
+                                   Gauss-Legendre rule of cell_quad points per
+                                   grid axis (cell_quad^dim kernel values per
+                                   offset; plan time grows accordingly).  The
+                                   offset-0 values (self and same-cell terms)
+                                   do not change.  Other values: EINVAL.     */
 } bemfft_plan_opts;
 
 /*

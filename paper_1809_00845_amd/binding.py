@@ -29,7 +29,7 @@ class bemfft_grid(ctypes.Structure):
 class bemfft_plan_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("c_mode", ctypes.c_int),
                 ("c_user", ctypes.POINTER(ctypes.c_double)), ("stream", ctypes.c_void_p),
-                ("keep_fp64", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("keep_fp64", ctypes.c_int), ("autotune", ctypes.c_int), ("cell_quad", ctypes.c_int)]
 
 
 class bemfft_solve_opts(ctypes.Structure):
@@ -199,7 +199,8 @@ def supported_sizes():
 
 
 def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.0, origin=(0.0, 0.0, 0.0),
-                       pad=(0, 0, 0), precision=FP64, c_mode=C_IMPLICIT, c_user=None, stream=None, keep_fp64=False, autotune=0):
+                       pad=(0, 0, 0), precision=FP64, c_mode=C_IMPLICIT, c_user=None, stream=None, keep_fp64=False, autotune=0,
+                       cell_quad=0):
     """Returns an opaque plan handle (ctypes.c_void_p)."""
     L = load()
     g = bemfft_grid()
@@ -228,6 +229,7 @@ def bemfft_plan_create(dim, n, h, nodes, normals, weights, kernel, nu=0.3, mu=1.
     opts.stream = _stream_ptr(stream) if stream is not None else None
     opts.keep_fp64 = 1 if keep_fp64 else 0
     opts.autotune = int(autotune)
+    opts.cell_quad = int(cell_quad)
     h_ = ctypes.c_void_p()
     st = L.bemfft_plan_create(ctypes.byref(h_), ctypes.byref(g), m,
                               nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -334,14 +336,14 @@ class Plan:
     normals/weights attributes."""
 
     def __init__(self, geom, kernel, precision=FP64, c_mode=C_IMPLICIT, c_user=None, nu=0.3, mu=1.0,
-                 pad=(0, 0, 0), stream=None, keep_fp64=False, autotune=0):
+                 pad=(0, 0, 0), stream=None, keep_fp64=False, autotune=0, cell_quad=0):
         self.kernel = kernel
         self.ncomp = 3 if kernel in (NAVIER3D, HALFSPACE) else 1
         self.m = int(np.asarray(geom.weights).shape[0])
         self.handle = bemfft_plan_create(geom.dim, geom.n, geom.h, geom.nodes, geom.normals, geom.weights,
                                          kernel, nu, mu, origin=geom.origin, pad=pad, precision=precision,
                                          c_mode=c_mode, c_user=c_user, stream=stream, keep_fp64=keep_fp64,
-                                         autotune=autotune)
+                                         autotune=autotune, cell_quad=cell_quad)
 
     def apply(self, q, u, r=None, stream=None):
         import torch

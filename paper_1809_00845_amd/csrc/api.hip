@@ -344,6 +344,8 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     }
     if (cmode < 0 || cmode > 2) { set_error("unknown c_mode"); return BEMFFT_EINVAL; }
     if (cmode == BEMFFT_C_USER && !(opts && opts->c_user)) { set_error("C_USER needs c_user"); return BEMFFT_EINVAL; }
+    const int cell_quad = opts ? opts->cell_quad : 0;
+    if (cell_quad < 0 || cell_quad > 8) { set_error("cell_quad must be in [0, 8]"); return BEMFFT_EINVAL; }
     hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
     const int d = ki.dim;
     p->dim = d;
@@ -357,6 +359,7 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     p->h = grid->h;
     p->nu = nu;
     p->mu = mu;
+    p->cell_quad = cell_quad;
     for (int a = 0; a < 3; ++a) {
         p->origin[a] = a < d ? grid->origin[a] : 0.0;
         p->n[a] = a < d ? grid->n[a] : 1;

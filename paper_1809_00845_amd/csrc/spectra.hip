@@ -6,7 +6,10 @@
 // is point-sampled at every padded-grid offset m (m_a in [-P_a/2, P_a/2)),
 // with the flat-panel value at m = 0 for the single layer (0 for the odd
 // double-layer kernels) and 0 on the planes m_a = -P_a/2, which no pair of
-// nodes reaches and whose zeroing keeps odd kernels exactly odd.  The
+// nodes reaches and whose zeroing keeps odd kernels exactly odd.  As a plan
+// option the values at m != 0 are instead the kernel's mean over the grid
+// cell centred on h m (the constant element taken literally), by a tensor
+// Gauss-Legendre rule; m = 0 and the zero planes are unchanged.  The
 // transform is FP64 always; one octant of the real (or imaginary) spectrum is
 // kept, because each kernel is even or odd along every axis.
 #include <hip/hip_runtime.h>
@@ -87,8 +90,48 @@ double kernel_k0(int kernel, int c, double h, double nu, double mu) {
     return 0.0;
 }
 
+// Gauss-Legendre rule on [-1/2, 1/2] with weights summing to 1 (q points;
+// q <= 1: the midpoint, i.e. point sampling).
+struct CellRule {
+    int q;
+    double x[8];
+    double w[8];
+};
+
+// Nodes by Newton's method on the Legendre polynomial P_q (three-term
+// recurrence), started from the asymptotic guesses cos(pi (i + 3/4) / (q + 1/2)).
+CellRule gauss_legendre_cell(int q) {
+    CellRule r{};
+    if (q <= 1) {
+        r.q = 1;
+        r.x[0] = 0.0;
+        r.w[0] = 1.0;
+        return r;
+    }
+    r.q = q;
+    for (int i = 0; i < q; ++i) {
+        double t = std::cos(kPi * (i + 0.75) / (q + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= q; ++k) {
+                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = q * (t * p1 - p0) / (t * t - 1.0);
+            double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) break;
+        }
+        r.x[i] = 0.5 * t;
+        r.w[i] = 1.0 / ((1.0 - t * t) * dp * dp);  // 2 / ((1 - t^2) P_q'(t)^2), halved
+    }
+    return r;
+}
+
 __global__ void k_sample(cx<double> *out, int64_t px, int64_t py, int64_t pz, int kernel, int c,
-                         double h, double nu, double mu, double k0, double scale) {
+                         double h, double nu, double mu, double k0, double scale, CellRule rule, int dim) {
     int64_t total = px * py * pz;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
@@ -100,7 +143,23 @@ __global__ void k_sample(cx<double> *out, int64_t px, int64_t py, int64_t pz, in
         double v;
         if (nyq) v = 0.0;
         else if (mx == 0 && my == 0 && mz == 0) v = k0;
-        else v = kernel_value(kernel, c, h * (double)mx, h * (double)my, h * (double)mz, nu, mu);
+        else if (rule.q <= 1) v = kernel_value(kernel, c, h * (double)mx, h * (double)my, h * (double)mz, nu, mu);
+        else {
+            // mean over the cell around h m
+            const int qz = dim == 3 ? rule.q : 1;
+            v = 0.0;
+            for (int a = 0; a < rule.q; ++a)
+                for (int b = 0; b < rule.q; ++b) {
+                    double s = 0.0;
+                    for (int e = 0; e < qz; ++e) {
+                        const double z = dim == 3 ? h * ((double)mz + rule.x[e]) : 0.0;
+                        const double we = dim == 3 ? rule.w[e] : 1.0;
+                        s += we * kernel_value(kernel, c, h * ((double)mx + rule.x[a]), h * ((double)my + rule.x[b]),
+                                               z, nu, mu);
+                    }
+                    v += rule.w[a] * rule.w[b] * s;
+                }
+        }
         out[idx] = {scale * v, 0.0};
     }
 }
@@ -255,11 +314,12 @@ int build_spectra(bemfft_plan *p, Engine *e64, Engine *e32, hipStream_t st) {
     double worst = 0.0;
     int status = 0;
     const double scale = (p->kernel == BEMFFT_HALFSPACE ? 1.0 : -1.0) / (double)full_n;
+    const CellRule rule = gauss_legendre_cell(p->cell_quad);
     for (int c = 0; c < p->K && status == 0; ++c) {
         double k0 = kernel_k0(p->kernel, c, p->h, p->nu, p->mu);
         int blocks = (int)std::min<int64_t>((full_n + 255) / 256, 65536);
         hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(256), 0, st, full, px, py, pz, p->kernel, c, p->h,
-                           p->nu, p->mu, k0, scale);
+                           p->nu, p->mu, k0, scale, rule, p->dim);
         if (hipGetLastError() != hipSuccess) { status = BEMFFT_EDEVICE; break; }
         status = fft3d_c2c_f64(reinterpret_cast<double *>(full), px, py, pz, -1, st);
         if (status) break;

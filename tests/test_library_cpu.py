@@ -89,6 +89,10 @@ def test_plan_validation_rejects_before_device_work(lib):
     _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, 4), B.EINVAL)
     # NULL normals are refused for the boundary families
     _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, None, g.weights, B.LAPLACE2D), B.EINVAL)
+    # cell rule outside [0, 8]
+    for q in (-1, 9):
+        _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
+                                             cell_quad=q), B.EINVAL)
 
 
 def test_null_arguments(lib):
