@@ -138,13 +138,13 @@ def bench_grid_eval(plan, q, u, info, steps):
 def bench_dirichlet_cg(B, I, dev):
     """The paper's solver (end of Sec. 4): CG on the symmetrised Dirichlet
     single-layer system, against GMRES on the same problem, both FP64 to a
-    1e-6 relative residual.  The 2D square has 250 grid points per side on a
-    256^2 grid (the largest the 512-point transforms allow; the paper's
-    Fig. 6 uses 500); the sphere is the 128^3 one."""
+    1e-6 relative residual.  The 2D square is the paper's Fig. 6 setting:
+    500 grid points per side on a 500^2 grid (1024-point transforms); the
+    sphere is the 128^3 one."""
     import torch
 
     res = {}
-    for name, g, kind, harm in (("square2d_250_per_side_256sq", I.square2d(256, 250), B.LAPLACE2D,
+    for name, g, kind, harm in (("square2d_500_per_side_500sq", I.square2d(500, 500), B.LAPLACE2D,
                                  I.harmonic_2d_x2y2),
                                 ("sphere_128cubed", I.sphere3d(128, 0.35), B.LAPLACE3D, I.harmonic_3d_xyz)):
         u = torch.tensor(harm(g)[0], device=dev)

@@ -106,7 +106,9 @@ typedef enum { BEMFFT_C_HALF = 0, BEMFFT_C_USER = 1, BEMFFT_C_IMPLICIT = 2 } bem
 /* Uniform grid: n[a] points per axis at origin + h * g, g in [0, n[a]).
  * dim = 2 uses n[0], n[1] (n[2] ignored).  pad[a] = padded FFT length per
  * axis; 0 picks the smallest supported even length >= 2 n[a] (Sec. 4 pads the
- * space for the FFT without fixing the size). */
+ * space for the FFT without fixing the size).  Supported lengths: 32, 64,
+ * 96, 128, 192, 256, 320, 384, 512, and 1024 on 2D grids; so n[a] <= 512 in
+ * 2D and <= 256 in 3D (EINVAL beyond, EUNSUPPORTED for other pad values). */
 typedef struct {
     int dim;
     int64_t n[3];
@@ -467,7 +469,8 @@ int bemfft_fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int d
 const char *bemfft_strerror(int status);
 const char *bemfft_last_error(void);
 
-/* Supported padded FFT lengths (fills up to cap entries; returns the count). */
+/* Supported padded FFT lengths (fills up to cap entries; returns the count);
+ * the last one, 1024, is for 2D grids only. */
 int bemfft_supported_sizes(int64_t *sizes, int cap);
 
 #ifdef __cplusplus

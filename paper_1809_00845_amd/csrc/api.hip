@@ -22,7 +22,7 @@ namespace bemfft {
 namespace {
 thread_local std::string g_last_error;
 constexpr double kPi = 3.141592653589793238462643383279502884;
-const int64_t kSizes[] = {32, 64, 96, 128, 192, 256, 320, 384, 512};
+const int64_t kSizes[] = {32, 64, 96, 128, 192, 256, 320, 384, 512, 1024};  // 1024: 2D only
 // A grid row holding this many nodes is x-transformed by FFT.
 constexpr int kDenseRow = 24;
 // When no other row holds more than this many nodes, the forward direct DFT
@@ -363,10 +363,14 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     for (int a = 0; a < 3; ++a) {
         p->origin[a] = a < d ? grid->origin[a] : 0.0;
         p->n[a] = a < d ? grid->n[a] : 1;
-        if (p->n[a] < 1 || p->n[a] > 256) { set_error("grid size per axis must be in [1, 256]"); return BEMFFT_EINVAL; }
+        const int64_t nmax = d == 2 ? 512 : 256;  // padded lengths up to 1024 (2D) / 512 (3D)
+        if (p->n[a] < 1 || p->n[a] > nmax) {
+            set_error("grid size per axis must be in [1, " + std::to_string(nmax) + "]");
+            return BEMFFT_EINVAL;
+        }
         if (a < d) {
             int64_t pad = grid->pad[a] ? grid->pad[a] : auto_pad(p->n[a]);
-            if (pad < 2 * p->n[a] - 1 || !fft_size_supported(pad) || pad == 1) {
+            if (pad < 2 * p->n[a] - 1 || !fft_size_supported(pad) || pad == 1 || (d == 3 && pad > 512)) {
                 set_error("padded length " + std::to_string(pad) + " on axis " + std::to_string(a) +
                           " is unsupported or shorter than 2n-1");
                 return BEMFFT_EUNSUPPORTED;

@@ -78,7 +78,7 @@ struct BatchIO {
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int mini(int a, int b) { return a < b ? a : b; }
-constexpr int kMaxPx = 512;          // largest padded length along x
+constexpr int kMaxPx = 1024;         // largest padded length along x (2D plans; 3D stop at 512)
 
 // Complex value stored in 16 bits per part (the intermediates Y and Z of the
 // 16-bit form); arithmetic stays FP32.
@@ -750,7 +750,7 @@ constexpr int kGatherLanes = 8;
 template <typename R, int KIND>
 __device__ __forceinline__ void gather_body(const ApplyArgs &a, const int bx) {
     constexpr int O = Terms<KIND>::O, L = kGatherLanes;
-    __shared__ cx<R> twx[kMaxPx];
+    __shared__ cx<R> twx[(KIND == 0 || KIND == 3) ? kMaxPx : kMaxPx / 2];  // 3D: px <= 512
     const cx<R> *gtwx = static_cast<const cx<R> *>(a.twx);
     for (int i = threadIdx.x; i < a.px; i += 256) twx[i] = gtwx[i];
     __syncthreads();
@@ -895,6 +895,14 @@ int launch_z(const ApplyArgs &a, hipStream_t st) {
         default: break;                                     \
     }
 
+// As BF_SIZE_SWITCH, plus length 1024 for the 2D families (grids of up to
+// 512 points per axis); 3D plans never reach it and do not compile it.
+#define BF_SIZE_SWITCH_K(KIND_, len, FN, ...)                              \
+    if constexpr (KIND_ == 0 || KIND_ == 3) {                              \
+        if ((len) == 1024) return FN<1024>(__VA_ARGS__);                   \
+    }                                                                      \
+    BF_SIZE_SWITCH(len, FN, __VA_ARGS__)
+
 template <typename R, int KIND>
 struct Launch {
     template <int P> static int fwd(const ApplyArgs &a, hipStream_t st) { return launch_fwd<R, P, KIND>(a, st); }
@@ -921,7 +929,7 @@ struct Launch {
         return 0;
     }
     static int dispatch_rows_inv(const ApplyArgs &a, hipStream_t st) {
-        BF_SIZE_SWITCH(a.px, rows_inv, a, st);
+        BF_SIZE_SWITCH_K(KIND, a.px, rows_inv, a, st);
         set_error("unsupported x length");
         return BEMFFT_EUNSUPPORTED;
     }
@@ -961,7 +969,7 @@ struct Launch {
         return 0;
     }
     static int dispatch_fwd(const ApplyArgs &a, hipStream_t st) {
-        BF_SIZE_SWITCH(a.py, fwd, a, st);
+        BF_SIZE_SWITCH_K(KIND, a.py, fwd, a, st);
         set_error("unsupported y length");
         return BEMFFT_EUNSUPPORTED;
     }
@@ -1009,6 +1017,9 @@ struct Launch {
         BF_HIP(hipGetLastError());
         if (g.max_nd > 0) {
             int s2 = BEMFFT_EUNSUPPORTED;
+            if constexpr (KIND == 0 || KIND == 3) {
+                if (g.px == 1024) s2 = brows<1024>(dm, io, g, st);
+            }
             switch (g.px) {
                 case 32: s2 = brows<32>(dm, io, g, st); break;
                 case 64: s2 = brows<64>(dm, io, g, st); break;
@@ -1024,6 +1035,9 @@ struct Launch {
             BF_CHECK(s2);
         }
         int s3 = BEMFFT_EUNSUPPORTED;
+        if constexpr (KIND == 0 || KIND == 3) {
+            if (g.py == 1024) s3 = bfwd<1024>(dm, io, g, st);
+        }
         switch (g.py) {
             case 32: s3 = bfwd<32>(dm, io, g, st); break;
             case 64: s3 = bfwd<64>(dm, io, g, st); break;
@@ -1056,6 +1070,9 @@ struct Launch {
         }
         BF_CHECK(s4);
         int s5 = BEMFFT_EUNSUPPORTED;
+        if constexpr (KIND == 0 || KIND == 3) {
+            if (g.py == 1024) s5 = binv<1024>(dm, io, g, st);
+        }
         switch (g.py) {
             case 32: s5 = binv<32>(dm, io, g, st); break;
             case 64: s5 = binv<64>(dm, io, g, st); break;
@@ -1071,6 +1088,9 @@ struct Launch {
         BF_CHECK(s5);
         if (g.max_nd > 0 && g.row_inv) {
             int s6 = BEMFFT_EUNSUPPORTED;
+            if constexpr (KIND == 0 || KIND == 3) {
+                if (g.px == 1024) s6 = brows_inv<1024>(dm, io, g, st);
+            }
             switch (g.px) {
                 case 32: s6 = brows_inv<32>(dm, io, g, st); break;
                 case 64: s6 = brows_inv<64>(dm, io, g, st); break;
@@ -1092,14 +1112,14 @@ struct Launch {
     }
 
     static int dispatch_rows(const ApplyArgs &a, hipStream_t st) {
-        BF_SIZE_SWITCH(a.px, rows, a, st);
+        BF_SIZE_SWITCH_K(KIND, a.px, rows, a, st);
         set_error("unsupported x length");
         return BEMFFT_EUNSUPPORTED;
     }
     // all_rows: store every row y < ny (the grid evaluation), not only those
     // that hold nodes (the apply)
     static int dispatch_inv_y(const ApplyArgs &a, int all_rows, hipStream_t st) {
-        BF_SIZE_SWITCH(a.py, inv_y, a, all_rows, st);
+        BF_SIZE_SWITCH_K(KIND, a.py, inv_y, a, all_rows, st);
         set_error("unsupported y length");
         return BEMFFT_EUNSUPPORTED;
     }

@@ -265,6 +265,9 @@ template <> struct Sched<384, 0> : FFTShape<384, 16, 8, 6, 8> {};
 template <> struct Sched<384, 1> : FFTShape<384, 32, 4, 4, 4, 6> {};
 template <> struct Sched<512, 0> : FFTShape<512, 32, 8, 8, 8> {};
 template <> struct Sched<512, 1> : FFTShape<512, 32, 16, 4, 8> {};
+// 1024 points: 2D plans only (grids of up to 512 points per axis)
+template <> struct Sched<1024, 0> : FFTShape<1024, 64, 16, 16, 4> {};
+template <> struct Sched<1024, 1> : FFTShape<1024, 64, 4, 16, 16> {};
 
 template <int P>
 using PencilShape = Sched<P, 0>;

@@ -241,6 +241,7 @@ int axis_pass(cx<double> *d, int axis, int64_t len, int64_t px, int64_t py, int6
         case 320: return launch_axis<320>(d, axis, px, py, pz, dir, st);
         case 384: return launch_axis<384>(d, axis, px, py, pz, dir, st);
         case 512: return launch_axis<512>(d, axis, px, py, pz, dir, st);
+        case 1024: return launch_axis<1024>(d, axis, px, py, pz, dir, st);
         default:
             set_error("FFT length " + std::to_string(len) + " is not supported");
             return BEMFFT_EUNSUPPORTED;
@@ -279,7 +280,7 @@ __global__ void k_to_f32(const double *in, float *out, int64_t n) {
 
 bool fft_size_supported(int64_t n) {
     switch (n) {
-        case 1: case 32: case 64: case 96: case 128: case 192: case 256: case 320: case 384: case 512:
+        case 1: case 32: case 64: case 96: case 128: case 192: case 256: case 320: case 384: case 512: case 1024:
             return true;
         default:
             return false;

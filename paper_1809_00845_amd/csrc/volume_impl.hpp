@@ -67,7 +67,7 @@ struct VolumeLaunch {
         return 0;
     }
     static int dispatch_x(const ApplyArgs &a, double *out, hipStream_t st) {
-        BF_SIZE_SWITCH(a.px, x, a, out, st);
+        BF_SIZE_SWITCH_K(KIND, a.px, x, a, out, st);
         set_error("unsupported x length");
         return BEMFFT_EUNSUPPORTED;
     }

@@ -110,3 +110,27 @@ def test_cg_rejects_navier_and_bad_options(dev):
     _, info = lap.solve_cg(u, tol=1e-14, maxit=2)
     assert info["status"] == B.ENOCONV and info["iters"] == 2
     lap.close()
+
+
+def test_cg_paper_square_500_per_side(dev):
+    """The paper's own experiment (end of Sec. 4, Fig. 6): the Dirichlet
+    problem on a square with 500 grid points per side (a 500^2 grid, padded
+    to 1024 per axis), solved by CG.  Checked against the oracle's LU
+    solution and the oracle's CG iteration count.  The paper reports about
+    5 iterations without giving its data or tolerance; the counts here are
+    for harmonic data x^2 - y^2 at 1e-10 and are context, not a match."""
+    g = I.square2d(500, 500)
+    u = I.harmonic_2d_x2y2(g)[0]
+    p = O.problem(g, O.LAPLACE2D)
+    q_lu = O.solve_lu(p, np.zeros(g.m, dtype=np.uint8), u)
+    plan = B.Plan(g, B.LAPLACE2D, precision=B.FP64)
+    assert plan.info()["pad"][0] == 1024
+    for precond in (0, 1):
+        _, it_orc = O.dirichlet_cg(p, u, tol=1e-10, precond=bool(precond))
+        q, info = plan.solve_cg(_t(u, dev), tol=1e-10, precond=precond)
+        q = q.cpu().numpy()
+        print(f"square 500/side, precond={precond}: GPU CG {info['iters']} iterations, oracle CG {it_orc}")
+        assert info["status"] == 0 and info["true_relres"] < 1e-9
+        assert np.linalg.norm(q - q_lu) <= 1e-7 * np.linalg.norm(q_lu)
+        assert abs(info["iters"] - it_orc) <= 2, (info["iters"], it_orc)
+    plan.close()

@@ -61,6 +61,14 @@ def test_halfspace_apply_vs_oracle(dev, case, precision):
 
 
 @pytest.mark.parametrize("precision", [B.FP64, B.FP32])
+def test_halfspace_512_surface_sampled(dev, precision):
+    # a 512^2 surface grid (P = 1024 per axis): disc of radius 0.45, first 200 targets
+    g = I.halfspace_patch(512, 0.45)
+    err, info = _parity(dev, g, precision, seed=2, targets=(0, 200))
+    assert info["pad"][0] == 1024 and err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [B.FP64, B.FP32])
 def test_halfspace_full_size_sampled(dev, precision):
     # the 256^2 surface (65,536 nodes, P = 512), first 300 targets
     g = I.halfspace_patch(256)

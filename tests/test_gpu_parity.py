@@ -62,7 +62,8 @@ def _parity(dev, g, kernel, precision, cmode=B.C_IMPLICIT, seed=0, cuser=None, n
 
 
 @pytest.mark.parametrize("shape", [(32, 1, 1), (64, 32, 1), (96, 1, 1), (128, 64, 1), (192, 1, 1),
-                                   (256, 32, 1), (320, 1, 1), (384, 1, 1), (512, 1, 1), (32, 64, 96)])
+                                   (256, 32, 1), (320, 1, 1), (384, 1, 1), (512, 1, 1), (32, 64, 96),
+                                   (1024, 1, 1), (1024, 64, 1), (32, 1024, 1)])
 def test_fft3d_vs_numpy(dev, shape):
     px, py, pz = shape
     rng = np.random.default_rng(1)
@@ -90,6 +91,16 @@ def test_laplace2d_circle_parity(dev, cmode):
         err, info = _parity(dev, g, B.LAPLACE2D, prec, cmode, cuser=cuser)
         assert err < TOL[prec], (prec, err)
         assert info["spectrum_parity_residual"] < 1e-14
+
+
+@pytest.mark.parametrize("case", ["square500", "circle512"])
+def test_laplace2d_padded_1024_parity(dev, case):
+    # grids of 500 and 512 points per axis: 1024-point transforms on both axes
+    g = I.square2d(500, 500) if case == "square500" else I.circle2d(512, 0.45)
+    for prec in (B.FP64, B.FP32):
+        err, info = _parity(dev, g, B.LAPLACE2D, prec, seed=9)
+        assert info["pad"][0] == 1024 and info["pad"][1] == 1024
+        assert err < TOL[prec], (case, prec, err)
 
 
 def test_laplace2d_config1_parity(dev):

@@ -82,6 +82,13 @@ def test_eval_grid_whole_box_vs_oracle(dev, case, precision):
     assert err < TOL[precision], (case, err)
 
 
+def test_eval_grid_2d_padded_1024_sampled(dev):
+    # the 500-per-side square on its 500^2 grid (P = 1024)
+    g = I.square2d(500, 500)
+    err, info, _, _ = _volume_parity(dev, g, B.LAPLACE2D, B.FP64, seed=6, sample=300)
+    assert info["pad"][0] == 1024 and err < TOL[B.FP64]
+
+
 def test_eval_grid_odd_row_count(dev):
     # 2D, ny odd: the last pencil of the x pass carries one row
     g = I.circle2d(45, 0.4)

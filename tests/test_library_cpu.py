@@ -41,7 +41,7 @@ def test_header_symbols_exported(lib):
 def test_strerror_and_sizes(lib):
     assert B.strerror(0) == "ok"
     assert "invalid" in B.strerror(B.EINVAL)
-    assert B.supported_sizes() == [32, 64, 96, 128, 192, 256, 320, 384, 512]
+    assert B.supported_sizes() == [32, 64, 96, 128, 192, 256, 320, 384, 512, 1024]
 
 
 def _expect(status_fn, code):
@@ -89,6 +89,14 @@ def test_plan_validation_rejects_before_device_work(lib):
     _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, 4), B.EINVAL)
     # NULL normals are refused for the boundary families
     _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, None, g.weights, B.LAPLACE2D), B.EINVAL)
+    # grid sizes: 2D up to 512 per axis (P = 1024), 3D up to 256 (P = 512)
+    sq = I.square2d(513, 500)
+    _expect(lambda: B.bemfft_plan_create(2, sq.n, sq.h, sq.nodes, sq.normals, sq.weights, B.LAPLACE2D), B.EINVAL)
+    s3 = I.sphere3d(16, 0.35)
+    _expect(lambda: B.bemfft_plan_create(3, (257, 16, 16), s3.h, s3.nodes, s3.normals, s3.weights, B.LAPLACE3D),
+            B.EINVAL)
+    _expect(lambda: B.bemfft_plan_create(3, s3.n, s3.h, s3.nodes, s3.normals, s3.weights, B.LAPLACE3D,
+                                         pad=(1024, 32, 32)), B.EUNSUPPORTED)
     # cell rule outside [0, 8]
     for q in (-1, 9):
         _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
