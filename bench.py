@@ -262,8 +262,9 @@ def cpu_baseline(geom, q, u, budget_s=12.0):
 def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
     """64 star surfaces (seed 2) on grids drawn from {64, 96, 128, 160}^3,
     4 right-hand sides each (Dirichlet data from random harmonic polynomials
-    of degree <= 3), FP32: batched apply (graph replay) and batched lockstep
-    GMRES to 1e-6, against per-plan applies and sequential plain FP64 solves."""
+    of degree <= 3): batched FP32 apply (graph replay) against per-plan
+    applies, and batched lockstep GMRES to 1e-6 against the same members
+    solved one at a time, at equal precision (FP32 and FP64)."""
     import tempfile
 
     import torch
@@ -317,33 +318,51 @@ def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
             p.apply(a, b_, c)
     torch.cuda.synchronize()
     dt_s = (time.perf_counter() - t0) / reps
-    # batched FP32 solve vs sequential plain FP64 solves
-    x = torch.zeros_like(known)
-    t0 = time.perf_counter()
-    st, sinfo = batch.solve(bcs, known, x, tol=1e-6, restart=100, maxit=1000)
-    torch.cuda.synchronize()
-    t_bsolve = time.perf_counter() - t0
+    # solves at equal precision: batched lockstep GMRES against the same
+    # members solved one at a time, in FP32 and in FP64
+    def seq_solves(plan_list):
+        total, iters = 0.0, []
+        for p_ in plan_list:
+            o, n = batch.offsets[len(iters)], batch.lengths[len(iters)]
+            p_.solve(bcs[o:o + n].contiguous(), known[o:o + n].contiguous(), tol=1e-6, restart=100,
+                     maxit=1000)  # warm: the plan's solve workspace
+            for _ in range(nrhs):
+                kk = len(iters)
+                o, n = batch.offsets[kk], batch.lengths[kk]
+                bck = bcs[o:o + n].contiguous()
+                knk = known[o:o + n].contiguous()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, si = p_.solve(bck, knk, tol=1e-6, restart=100, maxit=1000)
+                torch.cuda.synchronize()
+                total += time.perf_counter() - t1
+                iters.append(si["iters"])
+        return total, iters
+
+    def batched_solve(bt):
+        x = torch.zeros_like(known)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_, info_ = bt.solve(bcs, known, x, tol=1e-6, restart=100, maxit=1000)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1, st_, info_
+
+    batched_solve(batch)  # warm: workspace of the batch
+    t_bsolve, st, sinfo = batched_solve(batch)
     its = [i["iters"] for i in sinfo]
-    t_seq = 0.0
-    seq_its = []
-    for g, p32 in zip(geoms, plans):
-        p64 = B.Plan(g, B.LAPLACE3D, precision=B.FP64)
-        for k in range(nrhs):
-            kk = len(seq_its)
-            o, n = batch.offsets[kk], batch.lengths[kk]
-            bck = bcs[o:o + n].contiguous()
-            knk = known[o:o + n].contiguous()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, si = p64.solve(bck, knk, tol=1e-6, restart=100, maxit=1000)
-            torch.cuda.synchronize()
-            t_seq += time.perf_counter() - t1
-            seq_its.append(si["iters"])
-        p64.close()
+    t_seq32, seq32_its = seq_solves(plans)
+    p64s = [B.Plan(g, B.LAPLACE3D, precision=B.FP64) for g in geoms]
+    batch64 = B.Batch(p64s, nrhs=nrhs, use_graph=True)
+    batched_solve(batch64)  # warm: workspace of the FP64 batch
+    t_b64, st64, sinfo64 = batched_solve(batch64)
+    t_seq, seq_its = seq_solves(p64s)
+    batch64.close()
+    for p_ in p64s:
+        p_.close()
     os.unlink(tune.name)
     sizes = sorted(set(n for n, _ in items))
     out = {
-        "workload": "64 star surfaces (seed 2), grids {64,96,128,160}^3 padded 2N, 4 Dirichlet RHS each, FP32",
+        "workload": "64 star surfaces (seed 2), grids {64,96,128,160}^3 padded 2N, 4 Dirichlet RHS each",
         "members": nm, "nodes_total": int(sum(g.m for g in geoms)),
         "grid_counts": {str(n): sum(1 for m_, _ in items if m_ == n) for n in sizes},
         "groups_by_pad_and_schedule": len(set((p.info()["pad"][0], p.info()["zsched"]) for p in plans)),
@@ -352,7 +371,13 @@ def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
         "batched_solve_fp32_s": t_bsolve, "batched_solve_status": st,
         "batched_solve_iters_max": int(max(its)), "batched_solve_iters_mean": float(np.mean(its)),
         "batched_solve_relres_max": float(max(i["true_relres"] for i in sinfo)),
+        "sequential_fp32_solves_s": t_seq32, "sequential_fp32_iters_mean": float(np.mean(seq32_its)),
+        "batched_vs_sequential_fp32": t_seq32 / t_bsolve,
+        "batched_solve_fp64_s": t_b64, "batched_solve_fp64_status": st64,
+        "batched_solve_fp64_iters_mean": float(np.mean([i["iters"] for i in sinfo64])),
+        "batched_solve_fp64_relres_max": float(max(i["true_relres"] for i in sinfo64)),
         "sequential_fp64_solves_s": t_seq, "sequential_fp64_iters_mean": float(np.mean(seq_its)),
+        "batched_vs_sequential_fp64": t_seq / t_b64,
         "setup_s": {"voxelise": t_geom, "plans": t_plan, "batch_and_graph": t_batch},
     }
     batch.close()
