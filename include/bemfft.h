@@ -127,11 +127,17 @@ typedef struct {
                                    (needed by FP64-refined solves of a lower-
                                    precision plan); default 0                */
     int autotune;               /* radix schedule of the z transform: 0 the
-                                   default one, 1 time both compiled
-                                   schedules on this plan and keep the faster
-                                   (cached per kernel/precision/padded size
-                                   in the file named by BEMFFT_TUNE_CACHE, if
-                                   set), 2 the alternative one              */
+                                   default one for the family, precision and
+                                   length, 1 time every compiled schedule on
+                                   this plan and keep the fastest (cached per
+                                   kernel/precision/padded size in the file
+                                   named by BEMFFT_TUNE_CACHE, if set),
+                                   2 + s schedule s: 0 and 1 (16 or 32 lanes
+                                   per pencil, by length) always exist; 2,
+                                   the wide one with 64 lanes per pencil,
+                                   only for Navier plans with padded z length
+                                   256, 384 or 512 (else the default is
+                                   kept).  Other values: EINVAL.            */
     int cell_quad;              /* kernel values at grid offsets m != 0
                                    (Sec. 4 / Fig. 5 discretises the kernels
                                    as constants per element): 0 or 1 the
@@ -369,8 +375,10 @@ typedef struct {
     double spectrum_parity_residual; /* max discarded (imag or real) part of
                                         the kernel spectra / max |spectrum|     */
     double plan_seconds;
-    int zsched;                  /* radix schedule in use for the z transform */
-    double tune_us[2];           /* autotune: mean apply time per schedule, us */
+    int zsched;                  /* radix schedule in use for the z transform
+                                    (0, 1 or 2)                               */
+    double tune_us[3];           /* autotune: mean apply time per schedule, us
+                                    (0 for schedules not timed)               */
 } bemfft_plan_info;
 
 int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info);

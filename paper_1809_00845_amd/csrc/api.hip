@@ -310,6 +310,8 @@ int implicit_free_term(bemfft_plan *p, const Engine &e64, hipStream_t st, std::v
 }
 
 int autotune_zsched(bemfft_plan *p, hipStream_t st);
+int num_zsched(const bemfft_plan *p);
+int default_zsched(const bemfft_plan *p);
 
 int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const double *nodes,
                      const double *normals, const double *weights, int kernel, double nu, double mu,
@@ -344,6 +346,7 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     }
     if (cmode < 0 || cmode > 2) { set_error("unknown c_mode"); return BEMFFT_EINVAL; }
     if (cmode == BEMFFT_C_USER && !(opts && opts->c_user)) { set_error("C_USER needs c_user"); return BEMFFT_EINVAL; }
+    if (opts && (opts->autotune < 0 || opts->autotune > 4)) { set_error("autotune must be in [0, 4]"); return BEMFFT_EINVAL; }
     const int cell_quad = opts ? opts->cell_quad : 0;
     if (cell_quad < 0 || cell_quad > 8) { set_error("cell_quad must be in [0, 8]"); return BEMFFT_EINVAL; }
     hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
@@ -563,8 +566,11 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     if (hipStreamSynchronize(st) != hipSuccess) { set_error("plan: stream sync failed"); return BEMFFT_EDEVICE; }
     const int tune = opts ? opts->autotune : 0;
     // the 16-bit z pass has one schedule (its transforms are matrix products)
-    if (tune == 2 && prec != BEMFFT_BF16_MFMA) p->zsched = 1;
-    else if (tune == 1 && p->dim == 3 && prec != BEMFFT_BF16_MFMA) BF_CHECK(autotune_zsched(p, st));
+    if (p->dim == 3 && prec != BEMFFT_BF16_MFMA) {
+        p->zsched = default_zsched(p);
+        if (tune >= 2 && tune - 2 < num_zsched(p)) p->zsched = tune - 2;
+        else if (tune == 1) BF_CHECK(autotune_zsched(p, st));
+    }
     p->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return 0;
 }
@@ -572,6 +578,32 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
 std::string tune_key(const bemfft_plan *p) {
     return std::to_string(p->kernel) + ":" + std::to_string(p->eng.precision) + ":" + std::to_string(p->P[0]) + "x" +
            std::to_string(p->P[1]) + "x" + std::to_string(p->P[2]);
+}
+
+// Compiled z schedules of a plan: the default and the alternative one, and
+// for the Navier family the wide one where the length has it.
+int num_zsched(const bemfft_plan *p) {
+    return (p->kernel == BEMFFT_NAVIER3D && has_wide_sched((int)p->P[2])) ? 3 : 2;
+}
+
+// Schedule used without autotuning, from z-pass times measured on MI355X
+// (Navier spheres and stars, median of single applies).  Navier keeps three
+// output transforms live per pencil, so its fastest schedule depends on the
+// precision and the length:
+//   P = 256: FP32 wide 240 us (32-lane 345), FP64 32-lane 345 us (wide 500);
+//   P = 384: FP32 32-lane 0.76 ms (wide 1.06, 16-lane 2.64),
+//            FP64 wide 1.86 ms (32-lane 3.67, 16-lane 3.69);
+//   P = 512: FP32 32-lane 1.50 ms (wide 2.57), FP64 wide 2.87 ms (32-lane 10.55).
+// Other Navier lengths take the 32-lane schedule; Laplace keeps schedule 0.
+int default_zsched(const bemfft_plan *p) {
+    if (p->kernel != BEMFFT_NAVIER3D) return 0;
+    const bool fp64 = p->eng.precision == BEMFFT_FP64;
+    switch (p->P[2]) {
+        case 256: return fp64 ? 1 : 2;
+        case 384:
+        case 512: return fp64 ? 2 : 1;
+        default: return 1;
+    }
 }
 
 int tune_cache_lookup(const std::string &key) {
@@ -584,7 +616,7 @@ int tune_cache_lookup(const std::string &key) {
     while (std::fscanf(f, "%127s %d", k, &v) == 2)
         if (key == k) found = v;
     std::fclose(f);
-    return (found == 0 || found == 1) ? found : -1;
+    return (found >= 0 && found <= 2) ? found : -1;
 }
 
 void tune_cache_store(const std::string &key, int v) {
@@ -600,8 +632,9 @@ void tune_cache_store(const std::string &key, int v) {
 // the faster one.
 int autotune_zsched(bemfft_plan *p, hipStream_t st) {
     const std::string key = tune_key(p);
+    const int nsched = num_zsched(p);
     const int cached = tune_cache_lookup(key);
-    if (cached >= 0) {
+    if (cached >= 0 && cached < nsched) {
         p->zsched = cached;
         return 0;
     }
@@ -622,7 +655,7 @@ int autotune_zsched(bemfft_plan *p, hipStream_t st) {
         hipEventCreate(&e1) != hipSuccess)
         status = BEMFFT_EDEVICE;
     const int reps = 20;
-    for (int sched = 0; sched < 2 && status == 0; ++sched) {
+    for (int sched = 0; sched < nsched && status == 0; ++sched) {
         p->zsched = sched;
         for (int i = 0; i < 3 && status == 0; ++i) status = launch_apply(p, p->eng, q, u, r, st);
         if (status) break;
@@ -643,7 +676,9 @@ int autotune_zsched(bemfft_plan *p, hipStream_t st) {
         if (status == BEMFFT_EDEVICE) set_error("autotune: HIP failure");
         return status;
     }
-    p->zsched = p->tune_us[1] < p->tune_us[0] ? 1 : 0;
+    p->zsched = 0;
+    for (int sched = 1; sched < nsched; ++sched)
+        if (p->tune_us[sched] < p->tune_us[p->zsched]) p->zsched = sched;
     tune_cache_store(key, p->zsched);
     return 0;
 }
@@ -757,8 +792,7 @@ int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {
     info->spectrum_parity_residual = p->parity_resid;
     info->plan_seconds = p->plan_seconds;
     info->zsched = p->zsched;
-    info->tune_us[0] = p->tune_us[0];
-    info->tune_us[1] = p->tune_us[1];
+    for (int i = 0; i < 3; ++i) info->tune_us[i] = p->tune_us[i];
     return 0;
 }
 

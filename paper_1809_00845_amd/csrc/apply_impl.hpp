@@ -41,7 +41,7 @@ struct ApplyArgs {
     int hzs;          // stored kz row length of the spectra (hz, or padded)
     int z0, nzo;
     int m;
-    int zsched;       // radix schedule of the z pass (0 or 1)
+    int zsched;       // radix schedule of the z pass (0, 1, or 2 where a wide one exists)
     int64_t off;      // batched apply: offset of this member's q, u, r
     int gid;          // batched apply: member index in the whole batch
     const int *gx, *gy, *gz, *rowptr, *perm;
@@ -937,7 +937,10 @@ struct Launch {
         return launch_inv_y<R, P, KIND>(a, all_rows, st);
     }
     template <int P> static int z(const ApplyArgs &a, hipStream_t st) {
-        return a.zsched ? launch_z<R, P, KIND, 1>(a, st) : launch_z<R, P, KIND, 0>(a, st);
+        if constexpr (KIND == 2 && has_wide_sched(P)) {
+            if (a.zsched == 2) return launch_z<R, P, KIND, 2>(a, st);
+        }
+        return a.zsched == 1 ? launch_z<R, P, KIND, 1>(a, st) : launch_z<R, P, KIND, 0>(a, st);
     }
 
     // Fields, forward x/y and the z pass: everything up to Z.  ev (optional):
@@ -1010,7 +1013,10 @@ struct Launch {
         return 0;
     }
     template <int P> static int bz(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
-        return g.zsched ? bz_s<P, 1>(dm, io, g, st) : bz_s<P, 0>(dm, io, g, st);
+        if constexpr (KIND == 2 && has_wide_sched(P)) {
+            if (g.zsched == 2) return bz_s<P, 2>(dm, io, g, st);
+        }
+        return g.zsched == 1 ? bz_s<P, 1>(dm, io, g, st) : bz_s<P, 0>(dm, io, g, st);
     }
     static int run_batch(const ApplyArgs *dm, const BatchIO *io, const GroupDims &g, hipStream_t st) {
         hipLaunchKernelGGL((kb_fields<R, KIND>), dim3((g.max_m + 255) / 256, 1, g.nmem), dim3(256), 0, st, dm, io, 1);

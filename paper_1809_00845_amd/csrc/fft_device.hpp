@@ -242,8 +242,11 @@ struct FFTShape {
     using rad = Radices<Rs...>;
 };
 
-// Two compiled schedules per length (S = 0 default, S = 1 alternative); the
-// plan's autotuner picks one for the z pass by timing both.
+// Two compiled schedules per length (S = 0 default, S = 1 alternative), and
+// for three lengths a wide one (S = 2: one pencil per wavefront, 64 lanes,
+// so a lane holds P/64 values -- for the z pass of the Navier family, whose
+// three FP64 output accumulators do not fit in registers at 16 or 32 lanes
+// per pencil); the plan's autotuner picks one for the z pass by timing them.
 template <int P, int S>
 struct Sched;
 template <> struct Sched<1, 0> : FFTShape<1, 1> {};
@@ -268,6 +271,12 @@ template <> struct Sched<512, 1> : FFTShape<512, 32, 16, 4, 8> {};
 // 1024 points: 2D plans only (grids of up to 512 points per axis)
 template <> struct Sched<1024, 0> : FFTShape<1024, 64, 16, 16, 4> {};
 template <> struct Sched<1024, 1> : FFTShape<1024, 64, 4, 16, 16> {};
+template <> struct Sched<256, 2> : FFTShape<256, 64, 4, 4, 4, 4> {};
+template <> struct Sched<384, 2> : FFTShape<384, 64, 6, 2, 2, 2, 2, 2, 2> {};
+template <> struct Sched<512, 2> : FFTShape<512, 64, 8, 8, 8> {};
+
+// Lengths with a wide schedule.
+__host__ __device__ constexpr bool has_wide_sched(int p) { return p == 256 || p == 384 || p == 512; }
 
 template <int P>
 using PencilShape = Sched<P, 0>;

@@ -99,7 +99,7 @@ struct bemfft_plan {
     double parity_resid = 0.0;
     int zsched = 0;               // radix schedule of the z transform
     int cell_quad = 0;            // kernel values at m != 0: 0 point, q >= 2 cell mean (q^dim points)
-    double tune_us[2] = {0, 0};
+    double tune_us[3] = {0, 0, 0};
     double plan_seconds = 0.0;
     // solve workspace, allocated on first use
     double *s_V = nullptr;

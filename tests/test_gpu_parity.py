@@ -432,27 +432,49 @@ def test_every_fft_length_both_schedules(dev, n):
     g = I.sphere3d(n, 0.35)
     m = g.m
     tg = (m // 3, min(m, m // 3 + 300))
-    for sched in (0, 2):
-        err, info = _parity(dev, g, B.LAPLACE3D, B.FP32, targets=tg, autotune=sched)
+    for sched in (0, 1):
+        err, info = _parity(dev, g, B.LAPLACE3D, B.FP32, targets=tg, autotune=2 + sched)
         assert info["pad"][2] == 2 * n
-        assert info["zsched"] == (1 if sched == 2 else 0)
+        assert info["zsched"] == sched
         assert err < TOL[B.FP32], (n, sched, err)
 
 
-def test_navier_alternative_schedule(dev):
+def test_navier_schedules_0_and_1(dev):
     g = I.sphere3d(24, 0.35)
+    for sched in (0, 1):
+        for prec in (B.FP64, B.FP32):
+            err, info = _parity(dev, g, B.NAVIER3D, prec, autotune=2 + sched)
+            assert info["zsched"] == sched and err < TOL[prec], (sched, prec, err)
+
+
+@pytest.mark.parametrize("n", [128, 192, 256])
+def test_navier_wide_schedule(dev, n):
+    """The wide z schedule (64 lanes per pencil) at its three lengths
+    (P = 256, 384, 512), FP64 and FP32, on 200 targets."""
+    g = I.sphere3d(n, 0.35)
+    tg = (g.m // 2, g.m // 2 + 200)
     for prec in (B.FP64, B.FP32):
-        err, info = _parity(dev, g, B.NAVIER3D, prec, autotune=2)
-        assert info["zsched"] == 1 and err < TOL[prec], (prec, err)
+        err, info = _parity(dev, g, B.NAVIER3D, prec, targets=tg, autotune=4)
+        assert info["pad"][2] == 2 * n and info["zsched"] == 2
+        assert err < TOL[prec], (n, prec, err)
+    # the default without autotuning: measured per precision and length
+    want = {128: (1, 2), 192: (2, 1), 256: (2, 1)}[n]
+    for prec, w in zip((B.FP64, B.FP32), want):
+        plan = B.Plan(g, B.NAVIER3D, precision=prec)
+        assert plan.info()["zsched"] == w
+        plan.close()
 
 
 def test_autotune_picks_a_schedule(dev):
-    g = I.sphere3d(64, 0.35)
-    plan = B.Plan(g, B.LAPLACE3D, precision=B.FP32, autotune=1)
-    info = plan.info()
-    assert info["zsched"] in (0, 1)
-    assert all(t > 0 for t in info["tune_us"])
-    assert info["tune_us"][info["zsched"]] == min(info["tune_us"])
+    # Laplace: two schedules; Navier at P = 256: three
+    for g, kind, ns in ((I.sphere3d(64, 0.35), B.LAPLACE3D, 2), (I.sphere3d(128, 0.35), B.NAVIER3D, 3)):
+        plan = B.Plan(g, kind, precision=B.FP32, autotune=1)
+        info = plan.info()
+        plan.close()
+        t = list(info["tune_us"])
+        assert all(x > 0 for x in t[:ns]) and all(x == 0 for x in t[ns:])
+        assert info["zsched"] in range(ns)
+        assert t[info["zsched"]] == min(t[:ns])
 
 
 # ------------------------------------------------------------------ batches
@@ -511,7 +533,8 @@ def test_batch_apply_other_kernels(dev, kind):
     and of half-space plans: every member equals its own plan's apply bit for
     bit (graph replayed twice), and one member matches the oracle."""
     if kind == "navier":
-        geoms = [I.sphere3d(12, 0.35), I.sphere3d(16, 0.3), I.cube3d(12, 8)]
+        # the 128^3 sphere (P = 256) runs the wide z schedule
+        geoms = [I.sphere3d(12, 0.35), I.sphere3d(16, 0.3), I.cube3d(12, 8), I.sphere3d(128, 0.35)]
         kern, okern, nc, prec = B.NAVIER3D, O.NAVIER3D, 3, B.FP64
     elif kind == "halfspace":
         # two discs and a full 160^2 surface, whose long rows take the row FFT

@@ -97,6 +97,10 @@ def test_plan_validation_rejects_before_device_work(lib):
             B.EINVAL)
     _expect(lambda: B.bemfft_plan_create(3, s3.n, s3.h, s3.nodes, s3.normals, s3.weights, B.LAPLACE3D,
                                          pad=(1024, 32, 32)), B.EUNSUPPORTED)
+    # autotune outside [0, 4]
+    for t in (-1, 5):
+        _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
+                                             autotune=t), B.EINVAL)
     # cell rule outside [0, 8]
     for q in (-1, 9):
         _expect(lambda: B.bemfft_plan_create(2, g.n, g.h, g.nodes, g.normals, g.weights, B.LAPLACE2D,
