@@ -439,7 +439,39 @@ def bench_navier_star(B, I, dev, steps):
     out["time_to_solve_1e-6"] = solves
     for pl in plans.values():
         pl.close()
+    out["mixed_bc_preconditioners"] = bench_navier_mixed(B, I, dev)
     return out
+
+
+def bench_navier_mixed(B, I, dev):
+    """The mixed Navier problem (displacement given above the centre,
+    traction below) on a 64^3 sphere, FP64 to 1e-6: scalar Jacobi against
+    the 3x3 block Jacobi of each node (the 192^3 star's mixed problem stalls
+    near 1e-5 with both; only its Dirichlet problem is timed above)."""
+    import torch
+
+    nu, mu = 0.3, 1.0
+    g = I.sphere3d(64, 0.35)
+    lam = 2 * mu * nu / (1 - 2 * nu)
+    E = np.random.default_rng(5).normal(size=(3, 3))
+    Es = 0.5 * (E + E.T)
+    uu = (g.rel() @ E.T).T
+    tt = (g.normals @ (lam * np.trace(Es) * np.eye(3) + 2 * mu * Es).T).T
+    bc = np.tile(I.mixed_bc_upper(g), (3, 1))
+    bct = torch.tensor(bc, device=dev)
+    known = torch.tensor(np.where(bc == 0, uu, tt), device=dev)
+    pl = B.Plan(g, B.NAVIER3D, precision=B.FP64, nu=nu, mu=mu)
+    res = {"workload": "Navier sphere 64^3 (%d nodes), mixed BC, FP64, GMRES(100) to 1e-6" % g.m}
+    for tag, pc in (("jacobi", 1), ("block_jacobi_3x3", 2)):
+        pl.solve(bct, known, tol=1e-6, precond=pc, maxit=3000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, si = pl.solve(bct, known, tol=1e-6, precond=pc, maxit=3000)
+        torch.cuda.synchronize()
+        res[tag] = {"seconds": time.perf_counter() - t0, "iters": si["iters"], "true_relres": si["true_relres"],
+                    "status": si["status"]}
+    pl.close()
+    return res
 
 
 def bench_cube_bf16(B, I, dev, cube, q, u, steps):

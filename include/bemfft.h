@@ -198,7 +198,11 @@ typedef struct {
     double tol;     /* stop when ||b - A x||_2 <= tol ||b||_2 (default 1e-6) */
     int restart;    /* Krylov basis size (default 100, max 400)               */
     int maxit;      /* total iterations (default 1000)                        */
-    int precond;    /* 0 none, 1 Jacobi (default 1)                           */
+    int precond;    /* right preconditioner: 0 none, 1 Jacobi (default), 2
+                       block Jacobi: the inverse of each node's 3x3 diagonal
+                       block of the mixed operator (-S_jj columns where q is
+                       unknown, C_j columns where u is unknown) for Navier
+                       plans, Jacobi for the others.  Batches: 0 or 1.   */
     int use_x0;     /* 0: start from x = 0; 1: 'unknown' holds the initial
                        guess on entry; 2: as 1, but the guess is kept only
                        if ||b - A x0|| < ||b|| (else x = 0: plain GMRES)  */
@@ -258,7 +262,8 @@ int bemfft_solve(bemfft_plan *p, const uint8_t *bc, const double *known, double 
  *     file-scope device array of BEMFFT_NOALLOC_SCRATCH_BYTES per GPU, held
  *     until the process ends; its address is looked up once per device, on
  *     the first call there;
- *   - limit: (restart + 10) * ncomp * m + 132096 doubles must fit in it, else
+ *   - limit: (restart + 10) * ncomp * m + 132096 doubles must fit in it
+ *     (restart + 13 with block Jacobi on a Navier plan), else
  *     EINVAL before any device work (the message names the largest restart
  *     for the plan): e.g. restart 100 for up to 36,929 unknowns, restart 30
  *     for up to 101,555;

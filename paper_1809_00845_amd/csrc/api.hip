@@ -460,10 +460,12 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     const int O = p->O;
     std::vector<double> C((size_t)m * O * O, 0.0), SC((size_t)m * O * O, 0.0);
     p->h_diag_dir.assign((size_t)O * m, 0.0);
+    p->h_self.assign((size_t)O * O * m, 0.0);
     for (int64_t s = 0; s < m; ++s) {
         double self[9], k0w[9], n3[3] = {snr[s], snr[m + s], snr[2 * m + s]};
         self_blocks(kernel, sw[s], n3, p->h, nu, mu, self, k0w);
         for (int i = 0; i < O * O; ++i) SC[(size_t)s * O * O + i] = self[i] - k0w[i];
+        for (int i = 0; i < O * O; ++i) p->h_self[(size_t)perm[s] * O * O + i] = self[i];
         for (int k = 0; k < O; ++k) p->h_diag_dir[(size_t)k * m + perm[s]] = -self[k * O + k];
     }
     int st_ = 0;

@@ -451,8 +451,8 @@ int bemfft_batch_solve(bemfft_batch *b, const uint8_t *bc, const double *known, 
     bemfft_solve_opts o{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
     if (opts) o = *opts;
     if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.refine || o.use_x0 < 0 ||
-        o.use_x0 > 1) {
-        set_error("batch_solve: bad options (refine and use_x0 = 2 are not supported for batches)");
+        o.use_x0 > 1 || o.precond < 0 || o.precond > 1) {
+        set_error("batch_solve: bad options (refine, use_x0 = 2 and block Jacobi are not supported for batches)");
         return BEMFFT_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;

@@ -96,6 +96,7 @@ struct bemfft_plan {
     bool has64 = false;        // an FP64 operator is available (eng or eng64)
     std::vector<double> h_c;   // c values in caller order (m or 9 m)
     std::vector<double> h_diag_dir, h_diag_neu;  // Jacobi entries per slot
+    std::vector<double> h_self;  // exact single-layer self blocks, caller order (m or 9 m)
     double parity_resid = 0.0;
     int zsched = 0;               // radix schedule of the z transform
     int cell_quad = 0;            // kernel values at m != 0: 0 point, q >= 2 cell mean (q^dim points)

@@ -68,6 +68,77 @@ __global__ void k_diag(const uint8_t *bc, const double *ddir, const double *dneu
     }
 }
 
+// Block Jacobi for three components per node: the diagonal block of the
+// mixed operator at node j has column b = -S_jj e_b where component b's q is
+// unknown (bc = 0) and C_j e_b where its u is unknown (the double-layer self
+// term is zero).  blk[j] receives the inverse of that 3x3 block (row-major),
+// from the adjugate; a block that is singular or not finite falls back to
+// the inverse of its diagonal (1 where that is 0).  selfb, cb: [m][9] in
+// caller order; blk may alias cb (each node reads its own entries first).
+__global__ void k_blk_build(const uint8_t *bc, const double *selfb, const double *cb, double *blk, int64_t m) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        double a[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                a[r * 3 + c] = bc[c * m + j] == 0 ? -selfb[j * 9 + r * 3 + c] : cb[j * 9 + r * 3 + c];
+        double inv[9];
+        inv[0] = a[4] * a[8] - a[5] * a[7];
+        inv[1] = a[2] * a[7] - a[1] * a[8];
+        inv[2] = a[1] * a[5] - a[2] * a[4];
+        inv[3] = a[5] * a[6] - a[3] * a[8];
+        inv[4] = a[0] * a[8] - a[2] * a[6];
+        inv[5] = a[2] * a[3] - a[0] * a[5];
+        inv[6] = a[3] * a[7] - a[4] * a[6];
+        inv[7] = a[1] * a[6] - a[0] * a[7];
+        inv[8] = a[0] * a[4] - a[1] * a[3];
+        const double det = a[0] * inv[0] + a[1] * inv[3] + a[2] * inv[6];
+        const double scale = fabs(a[0]) + fabs(a[4]) + fabs(a[8]);
+        const bool ok = isfinite(det) && fabs(det) > 1e-12 * scale * scale * scale;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            double v;
+            if (ok) v = inv[i] / det;
+            else v = (i % 4 == 0 && a[i] != 0.0 && isfinite(a[i])) ? 1.0 / a[i] : (i % 4 == 0 ? 1.0 : 0.0);
+            blk[j * 9 + i] = v;
+        }
+    }
+}
+
+// z_j = blk[j] x_j per node (x, z: [3][m]) and the split of z into the
+// unknown slots of (q, u): q where bc = 0, u where bc = 1.
+__device__ __forceinline__ void blk_split_node(const uint8_t *bc, const double *blk, const double x[3], double *q,
+                                               double *u, int64_t m, int64_t j) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double *b = blk + j * 9 + a * 3;
+        const double z = b[0] * x[0] + b[1] * x[1] + b[2] * x[2];
+        const bool qslot = bc[a * m + j] == 0;
+        q[a * m + j] = qslot ? z : 0.0;
+        u[a * m + j] = qslot ? 0.0 : z;
+    }
+}
+
+__global__ void k_split_blk(const uint8_t *bc, const double *x, const double *blk, double *q, double *u, int64_t m) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        const double xv[3] = {x[j], x[m + j], x[2 * m + j]};
+        blk_split_node(bc, blk, xv, q, u, m, j);
+    }
+}
+
+// y_j = blk[j] y_j in place (y: [3][m]).
+__global__ void k_mul_blk(double *y, const double *blk, int64_t m) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        const double x0 = y[j], x1 = y[m + j], x2 = y[2 * m + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double *b = blk + j * 9 + a * 3;
+            y[a * m + j] = b[0] * x0 + b[1] * x1 + b[2] * x2;
+        }
+    }
+}
+
 // partial[blk][j] = sum over this block's rows of V[j][i] w[i], j < nvec.
 // blockIdx.y picks a group of eight vectors, so every group's loads are in
 // flight at once; wavefront sums by lane shuffles, then one LDS step across
@@ -275,6 +346,33 @@ __global__ __launch_bounds__(256) void k_split_norm_r(const uint8_t *bc, const d
     }
 }
 
+// As k_split_norm_r, with the block-Jacobi scaling: one thread per node.
+// The basis column v = w / ||w|| is the same, bit for bit.
+__global__ __launch_bounds__(256) void k_split_norm_blk(const uint8_t *bc, const double *w, const double *pnorm,
+                                                        int nblk, const double *blk, double *v_out, double *q,
+                                                        double *u, int64_t m) {
+    __shared__ double nrm[1];
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 64) s += pnorm[b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) nrm[0] = sqrt(s);
+    }
+    __syncthreads();
+    const double a = nrm[0];
+    const double inv = a > 0.0 ? 1.0 / a : 0.0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        double v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = w[c * m + j] * inv;
+            v_out[c * m + j] = v[c];
+        }
+        blk_split_node(bc, blk, v, q, u, m, j);
+    }
+}
+
 // out = sqrt(sum of the norm partials) (same order as k_split_norm_r); then,
 // if flag is given (pinned host memory), the step's sequence number is
 // stored there with system-scope release: everything the step wrote for the
@@ -334,8 +432,13 @@ int grid_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); 
 
 struct Ws {
     double *V, *b, *x, *w, *q, *u, *r, *dinv, *ro, *d, *red, *hd;
+    double *blk;  // block-Jacobi inverses, [m][9] (three components per node)
+    bool blkmode;
     int cap;
 };
+
+// Block Jacobi in use: asked for, on a plan with three components per node.
+bool block_mode(const bemfft_plan *p, int precond) { return precond == 2 && p->ncomp == 3; }
 
 int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
     const int64_t n = (int64_t)p->ncomp * p->m;
@@ -350,7 +453,7 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
         p->s_cap = restart + 1;
     }
     if (!p->s_vec) {
-        if (hipMalloc(&p->s_vec, 9 * (size_t)n * sizeof(double)) != hipSuccess ||
+        if (hipMalloc(&p->s_vec, 12 * (size_t)n * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->s_red, (size_t)kRedBlocks * 512 * sizeof(double)) != hipSuccess ||
             hipMalloc(&p->s_hbuf, 2 * 512 * sizeof(double)) != hipSuccess ||
             hipHostMalloc(&p->h_pinned, 4 * 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -369,6 +472,7 @@ int ensure_workspace(bemfft_plan *p, int restart, Ws &ws) {
     ws.dinv = ws.r + n;
     ws.ro = ws.dinv + n;
     ws.d = ws.ro + n;
+    ws.blk = ws.d + n;  // 3 n doubles
     ws.red = p->s_red;
     ws.hd = p->s_hbuf;
     return 0;
@@ -486,11 +590,22 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
             double *vk = ws.V + (int64_t)kk * n;
             double *hc = col_of(kk);
             // w = A Dinv v_k; for k > 0, v_k = w / ||w|| of the previous step
+            const int64_t m = p->m;
             if (kk == 0) {
-                BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
+                if (ws.blkmode) {
+                    hipLaunchKernelGGL(k_split_blk, dim3(grid_for(m)), dim3(256), 0, st, bc, vk, ws.blk, ws.q, ws.u, m);
+                    BF_HIP(hipGetLastError());
+                    BF_CHECK(launch_apply(p, e, ws.q, ws.u, ws.w, st));
+                } else {
+                    BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
+                }
             } else {
-                hipLaunchKernelGGL(k_split_norm_r, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, red3, gc, ws.dinv, vk,
-                                   ws.q, ws.u, n, (double *)nullptr);
+                if (ws.blkmode)
+                    hipLaunchKernelGGL(k_split_norm_blk, dim3(grid_for(m)), dim3(256), 0, st, bc, ws.w, red3, gc,
+                                       ws.blk, vk, ws.q, ws.u, m);
+                else
+                    hipLaunchKernelGGL(k_split_norm_r, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, red3, gc, ws.dinv,
+                                       vk, ws.q, ws.u, n, (double *)nullptr);
                 BF_HIP(hipGetLastError());
                 BF_CHECK(launch_apply(p, e, ws.q, ws.u, ws.w, st));
             }
@@ -561,7 +676,8 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         BF_HIP(hipMemcpyAsync(ws.hd, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
         BF_HIP(hipMemsetAsync(ws.r, 0, n * sizeof(double), st));
         hipLaunchKernelGGL(k_gemv, dim3(grid_for(n)), dim3(256), 0, st, ws.V, n, k, ws.hd, ws.r, n, 1.0);
-        hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(256), 0, st, ws.r, ws.dinv, n);
+        if (ws.blkmode) hipLaunchKernelGGL(k_mul_blk, dim3(grid_for(p->m)), dim3(256), 0, st, ws.r, ws.blk, p->m);
+        else hipLaunchKernelGGL(k_mul, dim3(grid_for(n)), dim3(256), 0, st, ws.r, ws.dinv, n);
         hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, x, ws.r, 1.0, 1.0, n);
         BF_HIP(hipGetLastError());
         x_zero = false;
@@ -709,7 +825,8 @@ int solve_check(const bemfft_plan *p, const uint8_t *bc, const double *known, co
     }
     o = bemfft_solve_opts{1e-6, 100, 1000, 1, 0, 0, 1e-4, 20};
     if (opts) o = *opts;
-    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.use_x0 < 0 || o.use_x0 > 2) {
+    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > 400 || o.maxit < 1 || o.use_x0 < 0 || o.use_x0 > 2 ||
+        o.precond < 0 || o.precond > 2) {
         set_error("solve: bad options");
         return BEMFFT_EINVAL;
     }
@@ -741,6 +858,19 @@ int solve_impl(bemfft_plan *p, const uint8_t *bc, const double *known, double *u
         BF_HIP(hipMemcpyAsync(dd, p->h_diag_dir.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
         BF_HIP(hipMemcpyAsync(dn, p->h_diag_neu.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_diag, dim3(grid_for(n)), dim3(256), 0, st, bc, dd, dn, ws.dinv, n, o.precond);
+        BF_HIP(hipGetLastError());
+    }
+    ws.blkmode = block_mode(p, o.precond);
+    if (ws.blkmode) {
+        // self blocks into w, q, u (3 n contiguous doubles), c blocks into blk
+        const int64_t m = p->m;
+        if (ws.q != ws.w + n || ws.u != ws.q + n) {
+            set_error("solve: workspace layout");
+            return BEMFFT_EDEVICE;
+        }
+        BF_HIP(hipMemcpyAsync(ws.w, p->h_self.data(), 9 * m * sizeof(double), hipMemcpyHostToDevice, st));
+        BF_HIP(hipMemcpyAsync(ws.blk, p->h_c.data(), 9 * m * sizeof(double), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_blk_build, dim3(grid_for(m)), dim3(256), 0, st, bc, ws.w, ws.blk, ws.blk, m);
         BF_HIP(hipGetLastError());
     }
     if (o.use_x0) BF_HIP(hipMemcpyAsync(ws.x, unknown, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -881,11 +1011,13 @@ extern "C" int bemfft_solve_noalloc(bemfft_plan *p, const uint8_t *bc, const dou
     bemfft_solve_opts o;
     BF_CHECK(solve_check(p, bc, known, unknown, opts, o));
     const int64_t n = (int64_t)p->ncomp * p->m;
-    const int64_t need = (int64_t)(o.restart + 1) * n + 9 * n + kRedDoubles + kHdDoubles;
+    const int64_t extra = block_mode(p, o.precond) ? 3 * n : 0;  // block-Jacobi inverses
+    const int64_t need = (int64_t)(o.restart + 1) * n + 9 * n + extra + kRedDoubles + kHdDoubles;
     if (need > kScratchDoubles) {
-        set_error("solve_noalloc: (restart + 10) * ncomp * m = " + std::to_string((int64_t)(o.restart + 10) * n) +
+        set_error("solve_noalloc: (restart + " + std::to_string(10 + extra / n) + ") * ncomp * m = " +
+                  std::to_string((int64_t)(o.restart + 10) * n + extra) +
                   " doubles exceeds the fixed workspace; largest restart for this plan: " +
-                  std::to_string(noalloc_max_restart(n)));
+                  std::to_string(noalloc_max_restart(n) - extra / n));
         return BEMFFT_EINVAL;
     }
     double *base = nullptr;
@@ -905,6 +1037,7 @@ extern "C" int bemfft_solve_noalloc(bemfft_plan *p, const uint8_t *bc, const dou
     ws.d = ws.ro + n;
     ws.V = ws.d + n;
     ws.cap = o.restart + 1;
+    ws.blk = ws.V + (int64_t)ws.cap * n;  // 3 n doubles when used
     return solve_impl(p, bc, known, unknown, o, info, (hipStream_t)stream, ws, g_noalloc_host[dev], false, t0);
 }
 
