@@ -518,14 +518,15 @@ def bench_learned(B, args):
     from paper_1809_00845_amd import learned as LS
 
     G, ntr, nte = args.learned_grid, args.learned_train, args.learned_test
+    quiet = getattr(args, "quiet", False)
     t0 = time.perf_counter()
     probs = LS.problem_set(G, ntr + nte, seed=3)
     t_geom = time.perf_counter() - t0
-    print(f"  voxelised {ntr + nte} stars at {G}^3 in {t_geom:.1f} s", flush=True)
+    print(f"  voxelised {ntr + nte} stars at {G}^3 in {t_geom:.1f} s", file=sys.stderr, flush=True)
     net = B.Net(G, (1, 2, 4, 8), seed=0)
     t0 = time.perf_counter()
-    train = LS.make_samples(net, probs[:ntr], progress=200)
-    test_s = LS.make_samples(net, probs[ntr:], progress=100)
+    train = LS.make_samples(net, probs[:ntr], progress=None if quiet else 200)
+    test_s = LS.make_samples(net, probs[ntr:], progress=None if quiet else 100)
     t_data = time.perf_counter() - t0
     e0 = LS.relative_error(net, test_s)
     # one training step, timed alone
@@ -538,7 +539,7 @@ def bench_learned(B, args):
         net.gradients(s.x, s.vox, s.tgt, s.wt)
     t_grad = (time.perf_counter() - t0) / 10
     t0 = time.perf_counter()
-    hist = LS.train(net, train, epochs=args.learned_epochs, lr=2e-3)
+    hist = LS.train(net, train, epochs=args.learned_epochs, lr=2e-3, progress_s=0 if quiet else 30.0)
     t_train = time.perf_counter() - t0
     e1 = LS.relative_error(net, test_s)
     del train, test_s
@@ -606,6 +607,7 @@ def main():
                     help="only the grid-box evaluation on the FP32 cube plan (for profilers)")
     ap.add_argument("--learned", action="store_true",
                     help="only the learned-start workload: train on GPU-solved star problems, then compare solves")
+    ap.add_argument("--no-learned", action="store_true", help="skip the reduced learned-start workload")
     ap.add_argument("--learned-grid", type=int, default=96)
     ap.add_argument("--learned-train", type=int, default=2000)
     ap.add_argument("--learned-test", type=int, default=200)
@@ -782,6 +784,13 @@ def main():
         if not args.no_batched:
             plan64.close()
             extra["batched_64_stars_4rhs"] = bench_batched(B, I, dev)
+        if not args.no_learned:
+            # the learned-start workload at reduced size (64^3 grid, 300
+            # training and 40 held-out stars); --learned runs the full one
+            print("  learned start, reduced ...", file=sys.stderr, flush=True)
+            la = argparse.Namespace(learned_grid=64, learned_train=300, learned_test=40, learned_epochs=3,
+                                    quiet=True)
+            extra["learned_start_reduced"] = bench_learned(B, la)
         out["extra"] = extra
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline(cube, qn, un)

@@ -12,6 +12,7 @@ on the GPU; this module only loops over problems and keeps statistics.
 from __future__ import annotations
 
 import math
+import sys
 import time
 
 import numpy as np
@@ -66,7 +67,7 @@ def make_samples(net, problems, tol=1e-8, keep_problem=False, progress=None):
         finally:
             plan.close()
         if progress and (i + 1) % progress == 0:
-            print(f"  samples {i + 1}/{len(problems)} ({time.perf_counter() - t0:.1f} s)", flush=True)
+            print(f"  samples {i + 1}/{len(problems)} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     return out
 
 
@@ -86,7 +87,8 @@ def train(net, samples, epochs: int, lr: float = 1e-3, seed: int = 0, progress_s
             step += 1
             if progress_s and time.perf_counter() - last > progress_s:
                 last = time.perf_counter()
-                print(f"  train step {step}/{total} loss {np.mean(ls):.4f} ({last - t0:.0f} s)", flush=True)
+                print(f"  train step {step}/{total} loss {np.mean(ls):.4f} ({last - t0:.0f} s)", file=sys.stderr,
+                      flush=True)
         hist.append(float(np.mean(ls)))
     return hist
 
