@@ -592,7 +592,8 @@ int num_zsched(const bemfft_plan *p) {
 // (Navier spheres and stars, median of single applies).  Navier keeps three
 // output transforms live per pencil, so its fastest schedule depends on the
 // precision and the length:
-//   P = 256: FP32 wide 240 us (32-lane 345), FP64 32-lane 345 us (wide 500);
+//   P = 256: FP32 16-lane 196 us (wide 240, 32-lane 347), FP64 32-lane 343 us
+//            (wide 499, 16-lane 933);
 //   P = 384: FP32 32-lane 0.76 ms (wide 1.06, 16-lane 2.64),
 //            FP64 wide 1.86 ms (32-lane 3.67, 16-lane 3.69);
 //   P = 512: FP32 32-lane 1.50 ms (wide 2.57), FP64 wide 2.87 ms (32-lane 10.55).
@@ -601,7 +602,7 @@ int default_zsched(const bemfft_plan *p) {
     if (p->kernel != BEMFFT_NAVIER3D) return 0;
     const bool fp64 = p->eng.precision == BEMFFT_FP64;
     switch (p->P[2]) {
-        case 256: return fp64 ? 1 : 2;
+        case 256: return fp64 ? 1 : 0;
         case 384:
         case 512: return fp64 ? 2 : 1;
         default: return 1;

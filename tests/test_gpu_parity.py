@@ -458,7 +458,7 @@ def test_navier_wide_schedule(dev, n):
         assert info["pad"][2] == 2 * n and info["zsched"] == 2
         assert err < TOL[prec], (n, prec, err)
     # the default without autotuning: measured per precision and length
-    want = {128: (1, 2), 192: (2, 1), 256: (2, 1)}[n]
+    want = {128: (1, 0), 192: (2, 1), 256: (2, 1)}[n]
     for prec, w in zip((B.FP64, B.FP32), want):
         plan = B.Plan(g, B.NAVIER3D, precision=prec)
         assert plan.info()["zsched"] == w
