@@ -317,25 +317,31 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
             for (int k = 0; k < XG; ++k)
 #pragma unroll
                 for (int f = 0; f < F; ++f) acc[k][f] = {R(0), R(0)};
+            // the x twiddles come from the block's LDS table when Px = Py
+            // (the same table), else through the caches
+            auto row_sum = [&](const cx<R> *twt) {
 #pragma unroll 4
-            for (int s = r0; s < r1; ++s) {
-                const int xg = a.gx[s];
-                R vv[F];
+                for (int s = r0; s < r1; ++s) {
+                    const int xg = a.gx[s];
+                    R vv[F];
 #pragma unroll
-                for (int f = 0; f < F; ++f) vv[f] = vf[f * a.m + s];
-                int idx = mod_small(kxa, xg, a.px, inv_px);
+                    for (int f = 0; f < F; ++f) vv[f] = vf[f * a.m + s];
+                    int idx = mod_small(kxa, xg, a.px, inv_px);
 #pragma unroll
-                for (int k = 0; k < XG; ++k) {
-                    const cx<R> w = gtwx[idx];  // through the caches
+                    for (int k = 0; k < XG; ++k) {
+                        const cx<R> w = twt[idx];
 #pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        acc[k][f].x += vv[f] * w.x;
-                        acc[k][f].y += vv[f] * w.y;
+                        for (int f = 0; f < F; ++f) {
+                            acc[k][f].x += vv[f] * w.x;
+                            acc[k][f].y += vv[f] * w.y;
+                        }
+                        idx += xg;
+                        if (idx >= a.px) idx -= a.px;
                     }
-                    idx += xg;
-                    if (idx >= a.px) idx -= a.px;
                 }
-            }
+            };
+            if (a.px == PY) row_sum(tw);
+            else row_sum(gtwx);
         }
 #pragma unroll
         for (int k = 0; k < XG; ++k)
