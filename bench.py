@@ -386,7 +386,7 @@ def bench_batched(B, I, dev, steps=20, count=64, nrhs=4):
     return out
 
 
-def bench_navier_star(B, I, dev, steps):
+def bench_navier_star(B, I, dev, steps, mixed=True):
     """Navier (Kelvin, nu = 0.3, mu = 1) on the star surface of seed 1 on a
     192^3 grid padded to 384^3: FP32, FP64 and 16-bit (BF16 storage, z
     transforms on the matrix cores) applies with the z pass against the HBM
@@ -439,7 +439,8 @@ def bench_navier_star(B, I, dev, steps):
     out["time_to_solve_1e-6"] = solves
     for pl in plans.values():
         pl.close()
-    out["mixed_bc_preconditioners"] = bench_navier_mixed(B, I, dev)
+    if mixed:
+        out["mixed_bc_preconditioners"] = bench_navier_mixed(B, I, dev)
     return out
 
 
@@ -595,6 +596,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true", help="only the 64-shape batched workload")
     ap.add_argument("--no-navier", action="store_true", help="skip the 192^3 Navier star workload")
     ap.add_argument("--navier-only", action="store_true", help="only the 192^3 Navier star workload (for profilers)")
+    ap.add_argument("--no-navier-mixed", action="store_true",
+                    help="skip the Navier mixed-problem preconditioner comparison (for profilers)")
     ap.add_argument("--bf16-only", action="store_true",
                     help="only the 16-bit cube applies (z pass on the matrix cores; for profilers)")
     ap.add_argument("--solve-only", action="store_true",
@@ -649,7 +652,7 @@ def main():
         print(json.dumps(bench_dirichlet_cg(B, I, dev)), flush=True)
         return
     if args.navier_only:
-        print(json.dumps(bench_navier_star(B, I, dev, args.steps)), flush=True)
+        print(json.dumps(bench_navier_star(B, I, dev, args.steps, mixed=not args.no_navier_mixed)), flush=True)
         return
     if args.solve_only:
         g = I.cube3d(128, 100)
