@@ -105,16 +105,6 @@ std::vector<cx<R>> twiddle_table(int64_t p) {
     return t;
 }
 
-// BF16 bit pattern of v: v rounded to FP32, then to 8 mantissa bits with
-// round to nearest, ties to even (v is finite).
-uint16_t bf16_bits(double v) {
-    const float f = (float)v;
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 int64_t auto_pad(int64_t n) {
     for (int64_t s : kSizes)
         if (s >= 2 * n) return s;
@@ -531,30 +521,13 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
         status = alloc_workspace(p, &e32);  // sets the element sizes
         if (!status) status = upload_twiddles(&e32, p);
         if (!status) {
-            // the FP64 spectra rounded once to the stored precision
-            const int64_t n = (int64_t)p->K * p->H[0] * p->H[1] * p->H[2];
-            std::vector<double> tmp(n);
-            std::vector<float> tmpf;
-            std::vector<uint16_t> tmph;
-            const void *src = nullptr;
-            if (hipMemcpy(tmp.data(), e64.spec, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            // the FP64 spectra rounded once to the stored precision, on the device
+            const int64_t hz = p->H[2], rows = (int64_t)p->K * p->H[0] * p->H[1];
+            status = convert_spectra(static_cast<const double *>(e64.spec), &e32, rows, hz, st);
+            if (!status && hipStreamSynchronize(st) != hipSuccess) {
+                set_error("spectrum conversion failed");
                 status = BEMFFT_EDEVICE;
-            } else if (prec == BEMFFT_FP32) {
-                tmpf.resize(n);
-                std::transform(tmp.begin(), tmp.end(), tmpf.begin(), [](double v) { return (float)v; });
-                src = tmpf.data();
-            } else {
-                // rows of hzs >= Hz values, zero beyond Hz
-                const int64_t hz = p->H[2], rows = n / hz;
-                tmph.assign((size_t)rows * e32.hzs, 0);
-                for (int64_t rw = 0; rw < rows; ++rw)
-                    for (int64_t k = 0; k < hz; ++k) tmph[(size_t)rw * e32.hzs + k] = bf16_bits(tmp[(size_t)rw * hz + k]);
-                src = tmph.data();
             }
-            const size_t sbytes = (size_t)p->K * p->H[0] * p->H[1] * e32.hzs * e32.sreal;
-            if (!status && hipMemcpy(e32.spec, src, sbytes, hipMemcpyHostToDevice) != hipSuccess)
-                status = BEMFFT_EDEVICE;
-            if (status) set_error("spectrum conversion failed");
         }
         if (status == 0 && opts && opts->keep_fp64) {
             p->eng64 = e64;  // the refinement's FP64 operator

@@ -120,6 +120,7 @@ int launch_apply(bemfft_plan *p, const Engine &e, const double *q, const double 
 // Spectrum precompute (spectra.hip): fills e64 (FP64) and, if e32 is
 // non-null, its rounded FP32 copy.
 int build_spectra(bemfft_plan *p, Engine *e64, Engine *e32, hipStream_t st);
+int convert_spectra(const double *in, Engine *e, int64_t rows, int64_t hz, hipStream_t st);
 int fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int dir, hipStream_t st);
 bool fft_size_supported(int64_t n);
 int upload_twiddles(Engine *e, const bemfft_plan *p);

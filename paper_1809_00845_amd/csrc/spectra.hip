@@ -253,27 +253,73 @@ __device__ void atomic_max_pos(unsigned long long *dst, double v) {
     atomicMax(dst, (unsigned long long)__double_as_longlong(v));
 }
 
-__global__ void k_extract(const cx<double> *full, double *out, int64_t px, int64_t py, int64_t hx,
-                          int64_t hy, int64_t hz, int imag, unsigned long long *stats) {
-    int64_t total = hx * hy * hz;
+// One octant of the real (or imaginary) part: out[kx][ky][kz] from
+// full[kz][ky][kx], through a 32 x 32 (kz, kx) LDS tile per block so that the
+// reads run along kx and the writes along kz.  The largest kept and
+// discarded magnitudes are reduced in the block and merged with one atomic
+// per block.  Grid: (ceil(hx/32), ceil(hz/32), hy), 256 threads.
+__global__ __launch_bounds__(256) void k_extract(const cx<double> *full, double *out, int64_t px, int64_t py,
+                                                 int64_t hx, int64_t hy, int64_t hz, int imag,
+                                                 unsigned long long *stats) {
+    __shared__ double tile[32][33];
+    __shared__ double red[2][4];
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    const int64_t kx0 = (int64_t)blockIdx.x * 32, kz0 = (int64_t)blockIdx.y * 32, ky = blockIdx.z;
     double kept = 0.0, disc = 0.0;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int64_t kz = idx % hz, ky = (idx / hz) % hy, kx = idx / (hz * hy);
-        cx<double> v = full[(kz * py + ky) * px + kx];
-        double a = imag ? v.y : v.x;
-        double b = imag ? v.x : v.y;
-        out[idx] = a;
-        kept = fmax(kept, fabs(a));
-        disc = fmax(disc, fabs(b));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t kz = kz0 + ty + 8 * i, kx = kx0 + tx;
+        double a = 0.0;
+        if (kz < hz && kx < hx) {
+            const cx<double> v = full[(kz * py + ky) * px + kx];
+            a = imag ? v.y : v.x;
+            kept = fmax(kept, fabs(a));
+            disc = fmax(disc, fabs(imag ? v.x : v.y));
+        }
+        tile[ty + 8 * i][tx] = a;
     }
-    atomic_max_pos(stats + 0, kept);
-    atomic_max_pos(stats + 1, disc);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t kx = kx0 + ty + 8 * i, kz = kz0 + tx;
+        if (kx < hx && kz < hz) out[(kx * hy + ky) * hz + kz] = tile[tx][ty + 8 * i];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        kept = fmax(kept, __shfl_xor(kept, off, 64));
+        disc = fmax(disc, __shfl_xor(disc, off, 64));
+    }
+    if (threadIdx.x % 64 == 0) {
+        red[0][threadIdx.x / 64] = kept;
+        red[1][threadIdx.x / 64] = disc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomic_max_pos(stats + 0, fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3])));
+        atomic_max_pos(stats + 1, fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3])));
+    }
 }
 
 __global__ void k_to_f32(const double *in, float *out, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = (float)in[i];
+}
+
+// BF16 bit pattern of v: rounded to FP32, then to 8 significant bits, round
+// to nearest, ties to even (v finite).  Rows of hz values are stored at a
+// stride of hzs (>= hz), zero beyond hz.
+__global__ void k_to_bf16_rows(const double *in, uint16_t *out, int64_t rows, int64_t hz, int64_t hzs) {
+    const int64_t n = rows * hzs;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / hzs, k = i % hzs;
+        uint16_t b = 0;
+        if (k < hz) {
+            unsigned u = __float_as_uint((float)in[r * hz + k]);
+            u += 0x7fffu + ((u >> 16) & 1u);
+            b = (uint16_t)(u >> 16);
+        }
+        out[i] = b;
+    }
 }
 
 }  // namespace
@@ -296,6 +342,23 @@ int fft3d_c2c_f64(double *data, int64_t px, int64_t py, int64_t pz, int dir, hip
     BF_CHECK(axis_pass(d, 0, px, px, py, pz, dir, st));
     BF_CHECK(axis_pass(d, 1, py, px, py, pz, dir, st));
     BF_CHECK(axis_pass(d, 2, pz, px, py, pz, dir, st));
+    return 0;
+}
+
+// The FP64 spectra rounded once to the working engine's stored precision,
+// on the device: FP32 contiguous, or BF16 rows of hz values at stride hzs.
+int convert_spectra(const double *in, Engine *e, int64_t rows, int64_t hz, hipStream_t st) {
+    const int64_t n = rows * (e->precision == BEMFFT_BF16_MFMA ? e->hzs : hz);
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    if (e->precision == BEMFFT_FP32)
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, st, in, static_cast<float *>(e->spec), n);
+    else
+        hipLaunchKernelGGL(k_to_bf16_rows, dim3(blocks), dim3(256), 0, st, in, static_cast<uint16_t *>(e->spec), rows,
+                           hz, e->hzs);
+    if (hipGetLastError() != hipSuccess) {
+        set_error("spectrum conversion failed");
+        return BEMFFT_EDEVICE;
+    }
     return 0;
 }
 
@@ -326,8 +389,8 @@ int build_spectra(bemfft_plan *p, Engine *e64, Engine *e32, hipStream_t st) {
         if (status) break;
         if (hipMemsetAsync(stats, 0, 2 * sizeof(unsigned long long), st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
         double *dst = static_cast<double *>(e64->spec) + (int64_t)c * oct;
-        int eb = (int)std::min<int64_t>((oct + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_extract, dim3(eb), dim3(256), 0, st, full, dst, px, py, hx, hy, hz,
+        const dim3 eg((unsigned)((hx + 31) / 32), (unsigned)((hz + 31) / 32), (unsigned)hy);
+        hipLaunchKernelGGL(k_extract, eg, dim3(256), 0, st, full, dst, px, py, hx, hy, hz,
                            comp_imag(p->kernel, c) ? 1 : 0, stats);
         unsigned long long hs[2];
         if (hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
