@@ -352,20 +352,37 @@ __global__ void k_pack16(const float *p, const int64_t *woff, const int64_t *bof
     if (i < 16) bp[l * 16 + i] = i < co[l] ? p[boff[l] + i] : 0.f;
 }
 
-// Tiles of 16 consecutive voxels; each wave keeps its 27 weight blocks in
-// registers and walks many tiles.  Blocks are mapped so that the 8 XCDs
-// (blocks go round-robin to them) each sweep one contiguous range of tiles:
-// the dilated taps then re-read planes that the same XCD's L2 just fetched.
-// Three accumulators (one per dz) keep three independent MFMA chains.
+// Tiles of 16 consecutive voxels; each wave keeps its weight operands in
+// registers and walks many tiles.  gfx950's 16x16x32 FP16 product takes two
+// taps per instruction (K = 2 x 16 input channels): for each (dy, dz) row the
+// dx = -1 and 0 taps share one product and dx = +1 takes one with a zero
+// second half, so a tile needs 18 products instead of 27.  Lane (j, kq) holds
+// voxel j's channels 8 (kq % 2) .. + 7 of the first tap (kq < 2) or of the
+// second (kq >= 2), loaded as one 16-byte word; neighbours outside the grid
+// are zero padding.  Blocks are mapped so that the 8 XCDs (blocks go round-
+// robin to them) each sweep one contiguous range of tiles: the dilated taps
+// then re-read planes that the same XCD's L2 just fetched.  Three
+// accumulators (one per dz) keep three independent MFMA chains.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
 template <bool LAST>
 __global__ __launch_bounds__(256) void k_conv16(const _Float16 *__restrict__ in, const _Float16 *__restrict__ Wp,
                                                 const float *__restrict__ bias, _Float16 *__restrict__ out,
                                                 float *__restrict__ y, int G, int d, int64_t ntiles) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = lane & 15, kq = lane >> 4;
-    h4 A[27];
+    const int half = 8 * (kq & 1);  // this lane's eight channels of its tap
+    const bool first = kq < 2;      // first tap of the pair (else the second)
+    const h8 zero8 = {};
+    // A operands: per (dz, dy) row, the pair (dx = -1, dx = 0) and (dx = +1, none)
+    h8 A[9][2];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) A[t] = *reinterpret_cast<const h4 *>(Wp + (t * 16 + j) * 16 + 4 * kq);
+    for (int rq = 0; rq < 9; ++rq) {
+        const int t0 = rq * 3;  // tap index q * 9 + r * 3 + (dx + 1), rq = q * 3 + r
+        const int ta = first ? t0 : t0 + 1;
+        A[rq][0] = *reinterpret_cast<const h8 *>(Wp + (ta * 16 + j) * 16 + half);
+        A[rq][1] = first ? *reinterpret_cast<const h8 *>(Wp + ((t0 + 2) * 16 + j) * 16 + half) : zero8;
+    }
     float br[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) br[r] = bias[4 * kq + r];
@@ -373,7 +390,6 @@ __global__ __launch_bounds__(256) void k_conv16(const _Float16 *__restrict__ in,
     const int xcd = blockIdx.x % 8, lb = blockIdx.x / 8, nlb = gridDim.x / 8;
     const int64_t per = (ntiles + 7) / 8;
     const int64_t t_lo = xcd * per, t_hi = (t_lo + per < ntiles) ? t_lo + per : ntiles;
-    const h4 zero = {(_Float16)0.f, (_Float16)0.f, (_Float16)0.f, (_Float16)0.f};
     for (int64_t tile = t_lo + (int64_t)lb * 4 + wave; tile < t_hi; tile += (int64_t)nlb * 4) {
         const int64_t v = tile * 16 + j;
         const bool valid = v < V;
@@ -382,39 +398,22 @@ __global__ __launch_bounds__(256) void k_conv16(const _Float16 *__restrict__ in,
         f4 acc[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-        // For each (dy, dz) row only the centre tap is loaded; the dx = -1 and
-        // +1 taps are the centre values of the lanes d to the left and right
-        // (the tile's 16 voxels are consecutive, so within one grid row lane
-        // j - d holds voxel v - d), fetched by lane shuffles.  Lanes whose
-        // neighbour lies outside the tile load it; neighbours outside the
-        // grid row are zero padding.
-        const int xl = x - d, xr = x + d;
-        const int srcl = (lane - d) & 63, srcr = (lane + d) & 63;
+        // pair 0: x - d (first) and x (second); pair 1: x + d (first), zero
+        const int xa = first ? x - d : x;
+        const int xb = x + d;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {  // dy = r - 1
-            const int y2 = yy + d * (r - 1);
+        for (int q = 0; q < 3; ++q) {  // dz = q - 1
+            const int zz = z + d * (q - 1);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int zz = z + d * (q - 1);
+            for (int r = 0; r < 3; ++r) {  // dy = r - 1
+                const int y2 = yy + d * (r - 1);
                 const bool row_ok = valid && y2 >= 0 && y2 < G && zz >= 0 && zz < G;
-                const _Float16 *rowp = in + (((int64_t)zz * G + y2) * G) * 16 + 4 * kq;
-                h4 bc = zero;
-                if (row_ok) bc = *reinterpret_cast<const h4 *>(rowp + (int64_t)x * 16);
-                double cbits;
-                __builtin_memcpy(&cbits, &bc, 8);
-                const double lbits = __shfl(cbits, srcl, 64), rbits = __shfl(cbits, srcr, 64);
-                h4 b_left = zero, b_right = zero;
-                if (row_ok && xl >= 0) {
-                    if (j >= d) __builtin_memcpy(&b_left, &lbits, 8);
-                    else b_left = *reinterpret_cast<const h4 *>(rowp + (int64_t)xl * 16);
-                }
-                if (row_ok && xr < G) {
-                    if (j + d < 16) __builtin_memcpy(&b_right, &rbits, 8);
-                    else b_right = *reinterpret_cast<const h4 *>(rowp + (int64_t)xr * 16);
-                }
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + r * 3 + 0], b_left, acc[q], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + r * 3 + 1], bc, acc[q], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16f16(A[q * 9 + r * 3 + 2], b_right, acc[q], 0, 0, 0);
+                const _Float16 *rowp = in + (((int64_t)zz * G + y2) * G) * 16 + half;
+                h8 b0 = zero8, b1 = zero8;
+                if (row_ok && xa >= 0) b0 = *reinterpret_cast<const h8 *>(rowp + (int64_t)xa * 16);
+                if (row_ok && first && xb < G) b1 = *reinterpret_cast<const h8 *>(rowp + (int64_t)xb * 16);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[q * 3 + r][0], b0, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[q * 3 + r][1], b1, acc[q], 0, 0, 0);
             }
         }
         if (valid) {
