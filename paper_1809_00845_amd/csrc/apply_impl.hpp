@@ -370,8 +370,10 @@ __device__ __forceinline__ void fwd_xy_body(const ApplyArgs &a, const int bx, co
 }
 
 template <typename R, int PY, int KIND, int XG, typename YS = cx<R>>
+// Grid (nzo, kx groups): consecutive blocks take consecutive planes of the
+// same kx group, so blocks in flight write neighbouring rows of Y.
 __global__ __launch_bounds__((FwdCfg<R, PY, KIND>::NT)) void k_fwd_xy(ApplyArgs a) {
-    fwd_xy_body<R, PY, KIND, XG, YS>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+    fwd_xy_body<R, PY, KIND, XG, YS>(a, blockIdx.y, blockIdx.x, blockIdx.z);
 }
 
 // Batched form: blockIdx.z = member * zdiv + the kernel's own z index.
@@ -857,7 +859,7 @@ __global__ __launch_bounds__(256) void kb_gather(const ApplyArgs *members, const
 template <typename R, int PY, int KIND, typename YS = cx<R>>
 int launch_fwd(const ApplyArgs &a, hipStream_t st) {
     using Cfg = FwdCfg<R, PY, KIND>;
-    dim3 grid((a.hx + Cfg::KXC - 1) / Cfg::KXC, a.nzo);
+    dim3 grid(a.nzo, (a.hx + Cfg::KXC - 1) / Cfg::KXC);
     if (a.fwd_xg == 2) hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 2, YS>), grid, dim3(Cfg::NT), 0, st, a);
     else hipLaunchKernelGGL((k_fwd_xy<R, PY, KIND, 1, YS>), grid, dim3(Cfg::NT), 0, st, a);
     BF_HIP(hipGetLastError());
