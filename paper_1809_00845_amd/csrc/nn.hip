@@ -8,8 +8,9 @@
 // operator applied to the known values, one application of eq. 16).
 // Layers: 3x3x3 convolutions with dilations d_l (zero padding), ReLU between
 // layers, one output channel read back at the node voxels as s h q.
-// Training (FP32 storage and arithmetic) minimises the weighted squared error
-// sum_j wt_j (y(v_j) - s h q_j)^2 against solved problems, with Adam.
+// Training (FP32 storage and arithmetic, the convolutions on the matrix
+// cores) minimises the weighted squared error sum_j wt_j (y(v_j) - s h q_j)^2
+// against solved problems, with Adam.
 // Inference (the guess) runs in FP16 on the matrix cores with FP32
 // accumulation.  The solve keeps the guess only when its residual is smaller
 // than ||b|| (plain GMRES from zero otherwise).
@@ -19,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -30,8 +32,9 @@ struct bemfft_net {
     std::vector<int64_t> woff, boff;
     int64_t nparam = 0;
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // params, grads, Adam moments
-    float *pre = nullptr, *post = nullptr;  // per layer [co][V] (post = relu(pre) for hidden layers)
-    float *ga = nullptr, *gb = nullptr;     // gradient ping-pong [width][V]
+    float *xcl = nullptr;                   // training input, channel-last [V][8]
+    float *pre = nullptr, *post = nullptr;  // per layer [V][co] (post = relu(pre) for hidden layers)
+    float *ga = nullptr, *gb = nullptr;     // gradient ping-pong [V][width]
     float *part = nullptr;                  // weight-gradient partial sums
     float *red = nullptr;                   // loss partial sums
     float *y = nullptr;                     // output of the last forward [V]
@@ -50,17 +53,13 @@ struct bemfft_net {
 namespace bemfft {
 namespace {
 
-constexpr int kChunk = 8192;  // voxels per weight-gradient block
+constexpr int kWgBlocks = 512;  // most weight-gradient blocks (partial sums) of a layer
 constexpr int64_t kMaxTargets = 65536LL * 256;  // loss partial sums: one per 256 targets
 
 __device__ __forceinline__ void vox_xyz(int64_t v, int G, int &x, int &y, int &z) {
     x = (int)(v % G);
     y = (int)((v / G) % G);
     z = (int)(v / ((int64_t)G * G));
-}
-
-__device__ __forceinline__ bool inside(int x, int y, int z, int G) {
-    return x >= 0 && x < G && y >= 0 && y < G && z >= 0 && z < G;
 }
 
 __global__ void k_fill(float *a, int64_t n, float v) {
@@ -98,154 +97,33 @@ __global__ void k_nn_input(const int *gx, const int *gy, const int *gz, const in
     atomicAdd(&x[5 * V + v], (float)(-ww * s * r[j]));
 }
 
-// out[c][v] = b[c] + sum_{ci, tap} W[c][ci][tap] in[ci][v + d tap]
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_fwd(const float *in, const float *W, const float *bias, float *pre,
-                                                  float *post, int G, int d, int relu) {
-    __shared__ float sW[COUT * CIN * 27];
-    __shared__ float sb[COUT];
-    for (int i = threadIdx.x; i < COUT * CIN * 27; i += 256) sW[i] = W[i];
-    for (int i = threadIdx.x; i < COUT; i += 256) sb[i] = bias[i];
-    __syncthreads();
-    const int64_t V = (int64_t)G * G * G;
-    const int64_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v >= V) return;
-    int x, y, z;
-    vox_xyz(v, G, x, y, z);
-    float acc[COUT];
-#pragma unroll
-    for (int c = 0; c < COUT; ++c) acc[c] = sb[c];
-    for (int ci = 0; ci < CIN; ++ci) {
-        const float *src = in + (int64_t)ci * V;
-#pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            const int xx = x + d * dx, yy = y + d * dy, zz = z + d * dz;
-            const float val = inside(xx, yy, zz, G) ? src[((int64_t)zz * G + yy) * G + xx] : 0.f;
-#pragma unroll
-            for (int c = 0; c < COUT; ++c) acc[c] += sW[(c * CIN + ci) * 27 + t] * val;
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < COUT; ++c) {
-        pre[(int64_t)c * V + v] = acc[c];
-        if (post) post[(int64_t)c * V + v] = relu ? fmaxf(acc[c], 0.f) : acc[c];
-    }
-}
-
-// gin[ci][v] = (sum_{c, tap} W[c][ci][tap] g[c][v - d tap]) * (prev_pre[ci][v] > 0)
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_bwd_data(const float *g, const float *W, const float *prev_pre,
-                                                       float *gin, int G, int d) {
-    __shared__ float sW[COUT * CIN * 27];
-    for (int i = threadIdx.x; i < COUT * CIN * 27; i += 256) sW[i] = W[i];
-    __syncthreads();
-    const int64_t V = (int64_t)G * G * G;
-    const int64_t v = blockIdx.x * 256 + threadIdx.x;
-    if (v >= V) return;
-    int x, y, z;
-    vox_xyz(v, G, x, y, z);
-    float acc[CIN];
-#pragma unroll
-    for (int c = 0; c < CIN; ++c) acc[c] = 0.f;
-    for (int c = 0; c < COUT; ++c) {
-        const float *src = g + (int64_t)c * V;
-#pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            const int xx = x - d * dx, yy = y - d * dy, zz = z - d * dz;
-            const float val = inside(xx, yy, zz, G) ? src[((int64_t)zz * G + yy) * G + xx] : 0.f;
-#pragma unroll
-            for (int k = 0; k < CIN; ++k) acc[k] += sW[(c * CIN + k) * 27 + t] * val;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < CIN; ++k) {
-        const int64_t idx = (int64_t)k * V + v;
-        gin[idx] = prev_pre[idx] > 0.f ? acc[k] : 0.f;
-    }
-}
-
-// Weight gradients of one layer, one chunk of voxels per block:
-// part[chunk][c][ci][tap] for the 9 taps of the block's dz plane, and the
-// bias gradient on the dz = 0 blocks (slot 27).  Wavefront shuffles, then a
-// fixed-order sum across the block: deterministic.
-template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_bwd_w(const float *g, const float *in, float *part, int G, int d) {
-    constexpr int NA = COUT * 9;
-    __shared__ float sm[4][NA + COUT];
-    const int64_t V = (int64_t)G * G * G;
-    const int chunk = blockIdx.x, ci = blockIdx.y, dzi = blockIdx.z;  // dz = dzi - 1
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    float acc[NA];
-    float accb[COUT];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) acc[i] = 0.f;
-#pragma unroll
-    for (int c = 0; c < COUT; ++c) accb[c] = 0.f;
-    const int64_t v0 = (int64_t)chunk * kChunk;
-    const int64_t v1 = (v0 + kChunk < V) ? v0 + kChunk : V;
-    const float *src = in + (int64_t)ci * V;
-    for (int64_t v = v0 + threadIdx.x; v < v1; v += 256) {
-        int x, y, z;
-        vox_xyz(v, G, x, y, z);
-        float gv[COUT];
-#pragma unroll
-        for (int c = 0; c < COUT; ++c) gv[c] = g[(int64_t)c * V + v];
-#pragma unroll
-        for (int t9 = 0; t9 < 9; ++t9) {
-            const int dx = t9 % 3 - 1, dy = t9 / 3 - 1, dz = dzi - 1;
-            const int xx = x + d * dx, yy = y + d * dy, zz = z + d * dz;
-            const float val = inside(xx, yy, zz, G) ? src[((int64_t)zz * G + yy) * G + xx] : 0.f;
-#pragma unroll
-            for (int c = 0; c < COUT; ++c) acc[c * 9 + t9] += gv[c] * val;
-        }
-        if (dzi == 1 && ci == 0) {
-#pragma unroll
-            for (int c = 0; c < COUT; ++c) accb[c] += gv[c];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_xor(acc[i], o, 64);
-#pragma unroll
-    for (int c = 0; c < COUT; ++c)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) accb[c] += __shfl_xor(accb[c], o, 64);
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NA; ++i) sm[wave][i] = acc[i];
-#pragma unroll
-        for (int c = 0; c < COUT; ++c) sm[wave][NA + c] = accb[c];
-    }
-    __syncthreads();
-    // part layout: [chunk][COUT][CIN][28]  (tap 0..26, bias in slot 27 of ci 0)
-    for (int i = threadIdx.x; i < NA; i += 256) {
-        const int c = i / 9, t9 = i % 9;
-        const float sum = (sm[0][i] + sm[1][i]) + (sm[2][i] + sm[3][i]);
-        part[(((int64_t)chunk * COUT + c) * CIN + ci) * 28 + dzi * 9 + t9] = sum;
-    }
-    if (dzi == 1 && ci == 0)
-        for (int c = threadIdx.x; c < COUT; c += 256)
-            part[(((int64_t)chunk * COUT + c) * CIN + 0) * 28 + 27] =
-                (sm[0][NA + c] + sm[1][NA + c]) + (sm[2][NA + c] + sm[3][NA + c]);
-}
-
-// gW[c][ci][t] = sum_chunks part; gb[c] likewise (fixed order)
-__global__ void k_conv_w_reduce(const float *part, int nchunk, int cin, int cout, float *gW, float *gb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// gW[c][ci][t] = sum over the chunks of part; gb[c] likewise.  A block
+// takes 32 outputs; eight groups of 32 threads sum eight contiguous slices
+// of the chunks, added in a fixed order: deterministic.
+__global__ __launch_bounds__(256) void k_conv_w_reduce(const float *part, int nchunk, int cin, int cout, float *gW,
+                                                       float *gb) {
+    __shared__ float sm[8][32];
+    const int o = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + o;
     const int nw = cout * cin * 27;
+    int off = -1;
     if (i < nw) {
         const int c = i / (cin * 27), r = i % (cin * 27), k = r / 27, t = r % 27;
-        float s = 0.f;
-        for (int ch = 0; ch < nchunk; ++ch) s += part[(((int64_t)ch * cout + c) * cin + k) * 28 + t];
-        gW[i] = s;
+        off = (c * cin + k) * 28 + t;
     } else if (i < nw + cout) {
-        const int c = i - nw;
-        float s = 0.f;
-        for (int ch = 0; ch < nchunk; ++ch) s += part[(((int64_t)ch * cout + c) * cin + 0) * 28 + 27];
-        gb[c] = s;
+        off = ((i - nw) * cin + 0) * 28 + 27;
+    }
+    const int per = (nchunk + 7) / 8, c0 = sl * per, c1 = c0 + per < nchunk ? c0 + per : nchunk;
+    const int64_t stride = (int64_t)cout * cin * 28;
+    float s = 0.f;
+    if (off >= 0)
+        for (int ch = c0; ch < c1; ++ch) s += part[ch * stride + off];
+    sm[sl][o] = s;
+    __syncthreads();
+    if (sl == 0 && off >= 0) {
+        const float tot = ((sm[0][o] + sm[1][o]) + (sm[2][o] + sm[3][o])) + ((sm[4][o] + sm[5][o]) + (sm[6][o] + sm[7][o]));
+        if (i < nw) gW[i] = tot;
+        else gb[i - nw] = tot;
     }
 }
 
@@ -430,14 +308,380 @@ __global__ __launch_bounds__(256) void k_conv16(const _Float16 *__restrict__ in,
     }
 }
 
+// ---------------------------------------------------------------- FP32 training on the matrix cores
+// Every layer trains as an implicit GEMM on gfx950's FP32 16x16x4 matrix
+// product: FP32 operands, FP32 accumulation.  Activations and their
+// gradients are channel-last: [V][16] for the hidden layers, [V][8] for the
+// input (channels 6 and 7 zero), [V] for the one-channel output; so a lane
+// fetches the channels of its products with one 8- or 16-byte load.
+// Operand layout (wave of 64): A[i][k] at lane i + 16 k, B[k][j] at lane
+// j + 16 k, D[i][j] at lane j + 16 (i / 4), element i % 4.  The K index of a
+// product is a summation index, so lane group k may hold any channel: with
+// CP stored channels, lane (j, k) of step s (NS = CP / 4 steps) takes
+// channel NS k + s.  Output rows beyond a layer's channels are zero.  Work
+// is split in contiguous ranges, ranked so that each of the 8 XCDs (blocks
+// go round-robin to them) sweeps one contiguous eighth of the grid: the
+// dilated taps then re-read planes its own L2 fetched.
+typedef float f2 __attribute__((ext_vector_type(2)));
+template <int N>
+using fvec = typename std::conditional<N == 4, f4, typename std::conditional<N == 2, f2, float>::type>::type;
+
+__device__ __forceinline__ int xcd_rank(int b, int nb) { return nb % 8 == 0 ? (b % 8) * (nb / 8) + b / 8 : b; }
+
+__device__ __forceinline__ float lane_elem(float v, int) { return v; }
+template <typename T>
+__device__ __forceinline__ float lane_elem(T v, int s) { return v[s]; }
+
+// Planar input [6][V] -> channel-last [V][8], channels 6 and 7 zero.
+__global__ void k_to_cl8(const float *x, int64_t V, float *o) {
+    const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    f4 a, b;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = x[c * V + v];
+    b[0] = x[4 * V + v];
+    b[1] = x[5 * V + v];
+    b[2] = 0.f;
+    b[3] = 0.f;
+    reinterpret_cast<f4 *>(o + v * 8)[0] = a;
+    reinterpret_cast<f4 *>(o + v * 8)[1] = b;
+}
+
+// Weight operands of one layer in LDS: sA[t][lane] holds lane (j, k)'s NS
+// values of tap t, W[j][NS k + s][t] (forward) or W[NS k + s][j][t] (data
+// gradient, transposed); zero beyond the layer's channels.
+template <int NS, bool TRANSPOSED>
+__device__ __forceinline__ void stage_weights(const float *__restrict__ W, int cin, int cout, fvec<NS> (*sA)[64]) {
+    for (int i = threadIdx.x; i < 27 * 64; i += blockDim.x) {
+        const int t = i / 64, ln = i % 64, jj = ln & 15, k = ln >> 4;
+        fvec<NS> a = {};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int c = NS * k + s;  // the K channel of this lane group and step
+            float w = 0.f;
+            if (!TRANSPOSED && jj < cout && c < cin) w = W[(jj * cin + c) * 27 + t];
+            if (TRANSPOSED && c < cout && jj < cin) w = W[(c * cin + jj) * 27 + t];
+            if constexpr (NS == 1) a = w;
+            else a[s] = w;
+        }
+        sA[t][ln] = a;
+    }
+}
+
+// One z plane (dz = q - 1, times SIGN) of a tile's taps: B[r * 3 + s3] holds
+// lane (j, k)'s NS channels of voxel (x + SIGN d dx, y + SIGN d dy, z + SIGN
+// d dz) of the channel-last array src (CP channels per voxel), zero outside
+// the grid or for lane groups beyond KMAX channels.
+template <int CP, int NS, int SIGN>
+__device__ __forceinline__ void load_plane(const float *__restrict__ src, int x, int y, int z, bool valid, int q, int G,
+                                           int d, int kq, fvec<NS> *B) {
+    const int zz = z + SIGN * d * (q - 1);
+    const bool zok = valid && NS * kq < CP && zz >= 0 && zz < G;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int y2 = y + SIGN * d * (r - 1);
+        const bool rok = zok && y2 >= 0 && y2 < G;
+        const int row = (zz * G + y2) * G;
+#pragma unroll
+        for (int s3 = 0; s3 < 3; ++s3) {
+            const int xx = x + SIGN * d * (s3 - 1);
+            B[r * 3 + s3] = fvec<NS>{};
+            if (rok && xx >= 0 && xx < G)
+                B[r * 3 + s3] = *reinterpret_cast<const fvec<NS> *>(src + (int64_t)(row + xx) * CP + NS * kq);
+        }
+    }
+}
+
+// Forward of one layer, out[v][c] = b[c] + sum_{ci, t} W[c][ci][t] in[v + d o_t][ci]:
+// per tap t, D (16 output channels x 16 consecutive voxels) += W_t (16 x CP)
+// in(. + d o_t) (CP x 16), NS products of four channels.
+template <int CIN, int CP, int COUT>
+__global__ __launch_bounds__(256) void k_conv_fwd_mx(const float *__restrict__ in, const float *__restrict__ W,
+                                                     const float *__restrict__ bias, float *__restrict__ pre,
+                                                     float *__restrict__ post, int G, int d, int relu, int ntiles) {
+    constexpr int NS = CP / 4;
+    typedef fvec<NS> VT;
+    __shared__ VT sA[27][64];
+    stage_weights<NS, false>(W, CIN, COUT, sA);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, kq = lane >> 4;
+    f4 br;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) br[r] = 4 * kq + r < COUT ? bias[4 * kq + r] : 0.f;
+    const int V = G * G * G;
+    const int nb = gridDim.x, per = (ntiles + nb - 1) / nb;
+    const int t_lo = xcd_rank(blockIdx.x, nb) * per;
+    const int t_hi = t_lo + per < ntiles ? t_lo + per : ntiles;
+    int tile = t_lo + wave;
+    VT Bc[9], Bn[9];
+    int x = 0, y = 0, z = 0, v = 0;
+    bool valid = false;
+    auto coords = [&](int tl, int &cx, int &cy, int &cz, int &cv, bool &cval) {
+        cv = tl * 16 + j;
+        cval = cv < V;
+        const int vv = cval ? cv : 0;
+        cx = vv % G;
+        cy = (vv / G) % G;
+        cz = vv / (G * G);
+    };
+    if (tile < t_hi) {
+        coords(tile, x, y, z, v, valid);
+        load_plane<CP, NS, 1>(in, x, y, z, valid, 0, G, d, kq, Bc);
+    }
+    for (; tile < t_hi; tile += 4) {
+        int xn = 0, yn = 0, zn = 0, vn = 0;
+        bool validn = false;
+        const bool more = tile + 4 < t_hi;
+        if (more) coords(tile + 4, xn, yn, zn, vn, validn);
+        f4 acc[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q < 2) load_plane<CP, NS, 1>(in, x, y, z, valid, q + 1, G, d, kq, Bn);
+            else if (more) load_plane<CP, NS, 1>(in, xn, yn, zn, validn, 0, G, d, kq, Bn);
+#pragma unroll
+            for (int s3 = 0; s3 < 3; ++s3)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const VT a = sA[q * 9 + r * 3 + s3][lane];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(lane_elem(a, s), lane_elem(Bc[r * 3 + s3], s),
+                                                                      acc[r], 0, 0, 0);
+                }
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Bc[e] = Bn[e];
+        }
+        if (valid) {
+            const f4 o = ((acc[0] + acc[1]) + acc[2]) + br;
+            if constexpr (COUT == 16) {
+                *reinterpret_cast<f4 *>(pre + (int64_t)v * 16 + 4 * kq) = o;
+                if (post) {
+                    f4 p;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) p[r] = relu ? fmaxf(o[r], 0.f) : o[r];
+                    *reinterpret_cast<f4 *>(post + (int64_t)v * 16 + 4 * kq) = p;
+                }
+            } else if (kq == 0) {
+                pre[v] = o[0];
+                if (post) post[v] = relu ? fmaxf(o[0], 0.f) : o[0];
+            }
+        }
+        x = xn;
+        y = yn;
+        z = zn;
+        v = vn;
+        valid = validn;
+    }
+}
+
+// Data gradient into a 16-channel layer, gin[v][ci] = (prev_pre[v][ci] > 0)
+// sum_{c, t} W[c][ci][t] g[v - d o_t][c]: per tap t, D (16 input channels x
+// 16 voxels) += W_t^T (16 x COUT) g(. - d o_t) (COUT x 16); the same plane
+// pipeline as the forward.
+template <int COUT>
+__global__ __launch_bounds__(256) void k_conv_bwd_data_mx(const float *__restrict__ g, const float *__restrict__ W,
+                                                          const float *__restrict__ prev_pre, float *__restrict__ gin,
+                                                          int G, int d, int ntiles) {
+    constexpr int NS = COUT == 16 ? 4 : 1;
+    typedef fvec<NS> VT;
+    __shared__ VT sA[27][64];
+    stage_weights<NS, true>(W, 16, COUT, sA);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, kq = lane >> 4;
+    const int V = G * G * G;
+    const int nb = gridDim.x, per = (ntiles + nb - 1) / nb;
+    const int t_lo = xcd_rank(blockIdx.x, nb) * per;
+    const int t_hi = t_lo + per < ntiles ? t_lo + per : ntiles;
+    int tile = t_lo + wave;
+    VT Bc[9], Bn[9];
+    int x = 0, y = 0, z = 0, v = 0;
+    bool valid = false;
+    auto coords = [&](int tl, int &cx, int &cy, int &cz, int &cv, bool &cval) {
+        cv = tl * 16 + j;
+        cval = cv < V;
+        const int vv = cval ? cv : 0;
+        cx = vv % G;
+        cy = (vv / G) % G;
+        cz = vv / (G * G);
+    };
+    if (tile < t_hi) {
+        coords(tile, x, y, z, v, valid);
+        load_plane<COUT, NS, -1>(g, x, y, z, valid, 0, G, d, kq, Bc);
+    }
+    for (; tile < t_hi; tile += 4) {
+        int xn = 0, yn = 0, zn = 0, vn = 0;
+        bool validn = false;
+        const bool more = tile + 4 < t_hi;
+        if (more) coords(tile + 4, xn, yn, zn, vn, validn);
+        f4 acc[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (q < 2) load_plane<COUT, NS, -1>(g, x, y, z, valid, q + 1, G, d, kq, Bn);
+            else if (more) load_plane<COUT, NS, -1>(g, xn, yn, zn, validn, 0, G, d, kq, Bn);
+#pragma unroll
+            for (int s3 = 0; s3 < 3; ++s3)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const VT a = sA[q * 9 + r * 3 + s3][lane];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        acc[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(lane_elem(a, s), lane_elem(Bc[r * 3 + s3], s),
+                                                                      acc[r], 0, 0, 0);
+                }
+#pragma unroll
+            for (int e = 0; e < 9; ++e) Bc[e] = Bn[e];
+        }
+        if (valid) {
+            const f4 o = (acc[0] + acc[1]) + acc[2];
+            const f4 pp = *reinterpret_cast<const f4 *>(prev_pre + (int64_t)v * 16 + 4 * kq);
+            f4 w;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] = pp[r] > 0.f ? o[r] : 0.f;
+            *reinterpret_cast<f4 *>(gin + (int64_t)v * 16 + 4 * kq) = w;
+        }
+        x = xn;
+        y = yn;
+        z = zn;
+        v = vn;
+        valid = validn;
+    }
+}
+
+// Weight and bias gradients of one layer, gW[c][ci][t] = sum_v g[v][c]
+// in[v + d o_t][ci]: per tap t, D (16 output channels x 16 input channels)
+// += g (16 x 4 voxels) in(. + d o_t)^T (4 x 16), four voxels per product,
+// one accumulator per tap.  A block walks slabs of kSlab voxels; lane (j, k)
+// of wave w keeps g of voxels 64 k + 16 w + i (i < 16, the K index of
+// product i) in registers for the whole slab.  Tap by tap, the slab's
+// shifted input (zero where the tap leaves the grid) is fetched with
+// coalesced 16-byte loads -- the next tap's into registers while the
+// current one is multiplied -- and stored transposed in LDS, [ci][u] with
+// padded rows, so that a lane reads the B values of four products with one
+// 16-byte LDS load (two buffers, one barrier per tap).  The four
+// wavefronts' sums are added through LDS in a fixed order into the block's
+// partial part[block][c][ci][28] (taps 0..26, bias in slot 27 of ci 0),
+// which k_conv_w_reduce adds up in a fixed order: deterministic.
+constexpr int kSlab = 256;
+
+template <int CIN, int CP, int COUT>
+__global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__ g, const float *__restrict__ in,
+                                                       float *__restrict__ part, int G, int d, int nslabs) {
+    constexpr int QV = CP / 4;            // 16-byte words per voxel of the input
+    constexpr int NF = kSlab * QV / 256;  // of them staged per thread and tap
+    constexpr int LD = kSlab + 4;         // padded row of the transposed slab
+    __shared__ __align__(16) float sT[2][CP * LD];
+    __shared__ float sR[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 15, kq = lane >> 4;
+    const int V = G * G * G, GG = G * G;
+    const int ubase = 64 * kq + 16 * wave;  // this lane's product voxels: ubase + i
+    f4 acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float accb = 0.f;  // bias of channel j from this lane's voxels
+    const int nb = gridDim.x, per = (nslabs + nb - 1) / nb;
+    const int s_lo = xcd_rank(blockIdx.x, nb) * per;
+    const int s_hi = s_lo + per < nslabs ? s_lo + per : nslabs;
+    for (int slab = s_lo; slab < s_hi; ++slab) {
+        const int v0 = slab * kSlab;
+        // staged words: f = tid + 256 i is voxel f / QV, channels 4 (f % QV) .. + 3
+        int ux[NF], uy[NF], uz[NF];
+        bool uval[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int vs = v0 + (tid + 256 * i) / QV;
+            uval[i] = vs < V;
+            const int vv = uval[i] ? vs : 0;
+            ux[i] = vv % G;
+            uy[i] = (vv / G) % G;
+            uz[i] = vv / GG;
+        }
+        auto fetch = [&](int t, f4 *R) {
+            const int dx = d * (t % 3 - 1), dy = d * ((t / 3) % 3 - 1), dz = d * (t / 9 - 1);
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const int f = tid + 256 * i;
+                const int xx = ux[i] + dx, yy = uy[i] + dy, zz = uz[i] + dz;
+                R[i] = f4{0.f, 0.f, 0.f, 0.f};
+                if (uval[i] && xx >= 0 && xx < G && yy >= 0 && yy < G && zz >= 0 && zz < G)
+                    R[i] = *reinterpret_cast<const f4 *>(in + ((int64_t)(zz * G + yy) * G + xx) * CP + 4 * (f % QV));
+            }
+        };
+        f4 R[NF];
+        fetch(0, R);
+        float a[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int vg = v0 + ubase + i;
+            a[i] = (j < COUT && vg < V) ? g[(int64_t)vg * COUT + (COUT == 16 ? j : 0)] : 0.f;
+            accb += a[i];
+        }
+        __syncthreads();  // the previous slab's products have read both buffers
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            float *T = sT[t & 1];
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const int f = tid + 256 * i, u = f / QV, c0 = 4 * (f % QV);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) T[(c0 + e) * LD + u] = R[i][e];
+            }
+            __syncthreads();
+            if (t < 26) fetch(t + 1, R);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                f4 b = f4{0.f, 0.f, 0.f, 0.f};
+                if (j < CP) b = *reinterpret_cast<const f4 *>(T + j * LD + ubase + 4 * h);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * h + e], b[e], acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // block sums in a fixed order
+    float *pb = part + (int64_t)blockIdx.x * COUT * CIN * 28;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sR[wave][lane * 4 + r] = acc[t][r];
+        __syncthreads();
+        {
+            const int i = tid, ln = i >> 2, c = 4 * (ln >> 4) + (i & 3), ci = ln & 15;
+            const float s = (sR[0][i] + sR[1][i]) + (sR[2][i] + sR[3][i]);
+            if (c < COUT && ci < CIN) pb[(c * CIN + ci) * 28 + t] = s;
+        }
+        __syncthreads();
+    }
+    accb += __shfl_xor(accb, 16, 64);
+    accb += __shfl_xor(accb, 32, 64);
+    if (kq == 0) sR[wave][j] = accb;
+    __syncthreads();
+    if (tid < COUT) pb[(tid * CIN + 0) * 28 + 27] = (sR[0][tid] + sR[1][tid]) + (sR[2][tid] + sR[3][tid]);
+}
+
 int grid1(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65535); }
 
-template <int CIN, int COUT>
+// Blocks for a sweep of n work items, about 'each' per block; above 8, a
+// multiple of 8 (one equal share per XCD).  cap is a multiple of 8.
+int mx_blocks(int64_t n, int64_t each, int cap) {
+    int64_t b = std::max<int64_t>(1, std::min<int64_t>((n + each - 1) / each, cap));
+    if (b > 8) b = (b + 7) / 8 * 8;
+    return (int)b;
+}
+
+template <int CIN, int CP, int COUT>
 int conv_fwd(const float *in, const float *W, const float *b, float *pre, float *post, int G, int d, int relu,
              hipStream_t st) {
     const int64_t V = (int64_t)G * G * G;
-    hipLaunchKernelGGL((k_conv_fwd<CIN, COUT>), dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, in, W, b, pre, post,
-                       G, d, relu);
+    const int ntiles = (int)((V + 15) / 16);
+    hipLaunchKernelGGL((k_conv_fwd_mx<CIN, CP, COUT>), dim3(mx_blocks(ntiles, 32, 2048)), dim3(256), 0, st, in, W, b,
+                       pre, post, G, d, relu, ntiles);
     BF_HIP(hipGetLastError());
     return 0;
 }
@@ -448,15 +692,17 @@ int layer_fwd(bemfft_net *n, int l, const float *in, hipStream_t st) {
     float *post = n->post + (int64_t)l * n->width * n->V;
     const int relu = l < n->nl - 1;
     const int ci = n->ci[l], co = n->co[l];
-    if (ci == 6 && co == 16) return conv_fwd<6, 16>(in, W, b, pre, post, n->G, n->dil[l], relu, st);
-    if (ci == 16 && co == 16) return conv_fwd<16, 16>(in, W, b, pre, post, n->G, n->dil[l], relu, st);
-    if (ci == 16 && co == 1) return conv_fwd<16, 1>(in, W, b, pre, post, n->G, n->dil[l], relu, st);
+    if (ci == 6 && co == 16) return conv_fwd<6, 8, 16>(in, W, b, pre, post, n->G, n->dil[l], relu, st);
+    if (ci == 16 && co == 16) return conv_fwd<16, 16, 16>(in, W, b, pre, post, n->G, n->dil[l], relu, st);
+    if (ci == 16 && co == 1) return conv_fwd<16, 16, 1>(in, W, b, pre, post, n->G, n->dil[l], relu, st);
     set_error("network: unsupported layer shape");
     return BEMFFT_EUNSUPPORTED;
 }
 
+// x: planar [6][V]; converted to the channel-last n->xcl first
 int forward(bemfft_net *n, const float *x, hipStream_t st) {
-    const float *in = x;
+    hipLaunchKernelGGL(k_to_cl8, dim3((unsigned)((n->V + 255) / 256)), dim3(256), 0, st, x, n->V, n->xcl);
+    const float *in = n->xcl;
     for (int l = 0; l < n->nl; ++l) {
         BF_CHECK(layer_fwd(n, l, in, st));
         in = n->post + (int64_t)l * n->width * n->V;
@@ -465,22 +711,24 @@ int forward(bemfft_net *n, const float *x, hipStream_t st) {
     return 0;
 }
 
-template <int CIN, int COUT>
+template <int CIN, int CP, int COUT>
 int bwd_w(const float *g, const float *in, float *part, int G, int d, float *gW, float *gb, hipStream_t st) {
     const int64_t V = (int64_t)G * G * G;
-    const int nch = (int)((V + kChunk - 1) / kChunk);
-    hipLaunchKernelGGL((k_conv_bwd_w<CIN, COUT>), dim3(nch, CIN, 3), dim3(256), 0, st, g, in, part, G, d);
+    const int nslabs = (int)((V + kSlab - 1) / kSlab);
+    const int nch = mx_blocks(nslabs, 2, kWgBlocks);
+    hipLaunchKernelGGL((k_conv_bwd_w_mx<CIN, CP, COUT>), dim3(nch), dim3(256), 0, st, g, in, part, G, d, nslabs);
     const int tot = COUT * CIN * 27 + COUT;
-    hipLaunchKernelGGL(k_conv_w_reduce, dim3((tot + 255) / 256), dim3(256), 0, st, part, nch, CIN, COUT, gW, gb);
+    hipLaunchKernelGGL(k_conv_w_reduce, dim3((tot + 31) / 32), dim3(256), 0, st, part, nch, CIN, COUT, gW, gb);
     BF_HIP(hipGetLastError());
     return 0;
 }
 
-template <int CIN, int COUT>
+template <int COUT>
 int bwd_d(const float *g, const float *W, const float *prev_pre, float *gin, int G, int d, hipStream_t st) {
     const int64_t V = (int64_t)G * G * G;
-    hipLaunchKernelGGL((k_conv_bwd_data<CIN, COUT>), dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, g, W,
-                       prev_pre, gin, G, d);
+    const int ntiles = (int)((V + 15) / 16);
+    hipLaunchKernelGGL((k_conv_bwd_data_mx<COUT>), dim3(mx_blocks(ntiles, 32, 2048)), dim3(256), 0, st, g, W, prev_pre,
+                       gin, G, d, ntiles);
     BF_HIP(hipGetLastError());
     return 0;
 }
@@ -497,19 +745,19 @@ int gradients(bemfft_net *n, const float *x, int64_t nt, const int *vox, const f
     std::vector<float> hred(nb);
     BF_HIP(hipMemcpyAsync(hred.data(), n->red, nb * sizeof(float), hipMemcpyDeviceToHost, st));
     for (int l = n->nl - 1; l >= 0; --l) {
-        const float *in = l == 0 ? x : n->post + (int64_t)(l - 1) * n->width * n->V;
+        const float *in = l == 0 ? n->xcl : n->post + (int64_t)(l - 1) * n->width * n->V;
         float *gW = n->g + n->woff[l], *gb = n->g + n->boff[l];
         const int ci = n->ci[l], co = n->co[l], d = n->dil[l];
         int s;
-        if (ci == 6 && co == 16) s = bwd_w<6, 16>(gcur, in, n->part, n->G, d, gW, gb, st);
-        else if (ci == 16 && co == 16) s = bwd_w<16, 16>(gcur, in, n->part, n->G, d, gW, gb, st);
-        else s = bwd_w<16, 1>(gcur, in, n->part, n->G, d, gW, gb, st);
+        if (ci == 6 && co == 16) s = bwd_w<6, 8, 16>(gcur, in, n->part, n->G, d, gW, gb, st);
+        else if (ci == 16 && co == 16) s = bwd_w<16, 16, 16>(gcur, in, n->part, n->G, d, gW, gb, st);
+        else s = bwd_w<16, 16, 1>(gcur, in, n->part, n->G, d, gW, gb, st);
         BF_CHECK(s);
         if (l > 0) {
             const float *W = n->p + n->woff[l];
             const float *prev_pre = n->pre + (int64_t)(l - 1) * n->width * n->V;
-            if (co == 16) s = bwd_d<16, 16>(gcur, W, prev_pre, gnext, n->G, d, st);
-            else s = bwd_d<16, 1>(gcur, W, prev_pre, gnext, n->G, d, st);
+            if (co == 16) s = bwd_d<16>(gcur, W, prev_pre, gnext, n->G, d, st);
+            else s = bwd_d<1>(gcur, W, prev_pre, gnext, n->G, d, st);
             BF_CHECK(s);
             std::swap(gcur, gnext);
         }
@@ -624,11 +872,12 @@ int bemfft_net_create(bemfft_net **out, int grid, int width, int nlayers, const 
         for (int i = 0; i < n->co[l]; ++i) hp.push_back(0.f);
     }
     n->nparam = (int64_t)hp.size();
-    const int nch = (int)((n->V + kChunk - 1) / kChunk);
+    const int nch = kWgBlocks;
     const size_t act = (size_t)nlayers * width * n->V * sizeof(float);
     if (hipMalloc(&n->p, n->nparam * 4) != hipSuccess || hipMalloc(&n->g, n->nparam * 4) != hipSuccess ||
         hipMalloc(&n->m, n->nparam * 4) != hipSuccess || hipMalloc(&n->v, n->nparam * 4) != hipSuccess ||
         hipMalloc(&n->pre, act) != hipSuccess || hipMalloc(&n->post, act) != hipSuccess ||
+        hipMalloc(&n->xcl, (size_t)8 * n->V * 4) != hipSuccess ||
         hipMalloc(&n->ga, (size_t)width * n->V * 4) != hipSuccess ||
         hipMalloc(&n->gb, (size_t)width * n->V * 4) != hipSuccess ||
         hipMalloc(&n->part, (size_t)nch * width * width * 28 * 4) != hipSuccess ||
@@ -654,7 +903,7 @@ int bemfft_net_create(bemfft_net **out, int grid, int width, int nlayers, const 
 
 int bemfft_net_destroy(bemfft_net *n) {
     if (!n) return 0;
-    for (float *q : {n->p, n->g, n->m, n->v, n->pre, n->post, n->ga, n->gb, n->part, n->red})
+    for (float *q : {n->p, n->g, n->m, n->v, n->xcl, n->pre, n->post, n->ga, n->gb, n->part, n->red})
         if (q) (void)hipFree(q);
     for (double *q : {n->dq, n->du, n->db, n->sdev})
         if (q) (void)hipFree(q);
