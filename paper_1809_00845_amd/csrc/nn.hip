@@ -560,7 +560,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_mx(const float *__restric
 // of wave w keeps g of voxels 64 k + 16 w + i (i < 16, the K index of
 // product i) in registers for the whole slab.  Tap by tap, the slab's
 // shifted input (zero where the tap leaves the grid) is fetched with
-// coalesced 16-byte loads -- the next tap's into registers while the
+// coalesced 16-byte loads -- the next two taps' into registers while the
 // current one is multiplied -- and stored transposed in LDS, [ci][u] with
 // padded rows, so that a lane reads the B values of four products with one
 // 16-byte LDS load (two buffers, one barrier per tap).  The four
@@ -613,8 +613,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
                     R[i] = *reinterpret_cast<const f4 *>(in + ((int64_t)(zz * G + yy) * G + xx) * CP + 4 * (f % QV));
             }
         };
-        f4 R[NF];
-        fetch(0, R);
+        f4 R0[NF], R1[NF];  // taps t and t + 1 in flight
+        fetch(0, R0);
+        fetch(1, R1);
         float a[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -626,6 +627,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
             float *T = sT[t & 1];
+            f4 *R = (t & 1) ? R1 : R0;
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 const int f = tid + 256 * i, u = f / QV, c0 = 4 * (f % QV);
@@ -633,7 +635,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
                 for (int e = 0; e < 4; ++e) T[(c0 + e) * LD + u] = R[i][e];
             }
             __syncthreads();
-            if (t < 26) fetch(t + 1, R);
+            if (t + 2 < 27) fetch(t + 2, R);
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 f4 b = f4{0.f, 0.f, 0.f, 0.f};
