@@ -385,9 +385,11 @@ __device__ __forceinline__ void load_plane(const float *__restrict__ src, int x,
 #pragma unroll
         for (int s3 = 0; s3 < 3; ++s3) {
             const int xx = x + SIGN * d * (s3 - 1);
-            B[r * 3 + s3] = fvec<NS>{};
-            if (rok && xx >= 0 && xx < G)
-                B[r * 3 + s3] = *reinterpret_cast<const fvec<NS> *>(src + (int64_t)(row + xx) * CP + NS * kq);
+            const bool ok = rok && xx >= 0 && xx < G;
+            // branch-free: an in-bounds load, then zero where the tap leaves the grid
+            // (keeps the loads in one block, so waits count only the loads needed)
+            const fvec<NS> val = *reinterpret_cast<const fvec<NS> *>(src + (ok ? (int64_t)(row + xx) * CP + NS * kq : 0));
+            B[r * 3 + s3] = ok ? val : fvec<NS>{};
         }
     }
 }
@@ -439,6 +441,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_mx(const float *__restrict__ i
         for (int r = 0; r < 3; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
+            __builtin_amdgcn_sched_barrier(0);  // one plane's weight words live at a time
             if (q < 2) load_plane<CP, NS, 1>(in, x, y, z, valid, q + 1, G, d, kq, Bn);
             else if (more) load_plane<CP, NS, 1>(in, xn, yn, zn, validn, 0, G, d, kq, Bn);
 #pragma unroll
@@ -522,6 +525,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_mx(const float *__restric
         for (int r = 0; r < 3; ++r) acc[r] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
+            __builtin_amdgcn_sched_barrier(0);  // one plane's weight words live at a time
             if (q < 2) load_plane<COUT, NS, -1>(g, x, y, z, valid, q + 1, G, d, kq, Bn);
             else if (more) load_plane<COUT, NS, -1>(g, xn, yn, zn, validn, 0, G, d, kq, Bn);
 #pragma unroll
@@ -556,17 +560,18 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_mx(const float *__restric
 // Weight and bias gradients of one layer, gW[c][ci][t] = sum_v g[v][c]
 // in[v + d o_t][ci]: per tap t, D (16 output channels x 16 input channels)
 // += g (16 x 4 voxels) in(. + d o_t)^T (4 x 16), four voxels per product,
-// one accumulator per tap.  A block walks slabs of kSlab voxels; lane (j, k)
-// of wave w keeps g of voxels 64 k + 16 w + i (i < 16, the K index of
-// product i) in registers for the whole slab.  Tap by tap, the slab's
-// shifted input (zero where the tap leaves the grid) is fetched with
-// coalesced 16-byte loads -- the next two taps' into registers while the
-// current one is multiplied -- and stored transposed in LDS, [ci][u] with
-// padded rows, so that a lane reads the B values of four products with one
-// 16-byte LDS load (two buffers, one barrier per tap).  The four
-// wavefronts' sums are added through LDS in a fixed order into the block's
-// partial part[block][c][ci][28] (taps 0..26, bias in slot 27 of ci 0),
-// which k_conv_w_reduce adds up in a fixed order: deterministic.
+// one accumulator per tap.  blockIdx.y picks the z offset of the taps (9
+// taps per block).  A block walks slabs of kSlab voxels; lane (j, k) of wave
+// w keeps g of voxels 64 k + 16 w + i (i < 16, the K index of product i) in
+// registers for the whole slab.  Tap by tap, the slab's shifted input (zero
+// where the tap leaves the grid) is fetched with coalesced 16-byte loads --
+// the next two taps' into registers while the current one is multiplied --
+// and stored transposed in LDS, [ci][u] with padded rows, so that a lane
+// reads the B values of four products with one 16-byte LDS load (two
+// buffers, one barrier per tap).  The four wavefronts' sums are added
+// through LDS in a fixed order into the partial part[blockIdx.x][c][ci][28]
+// (taps 0..26, bias in slot 27 of ci 0), which k_conv_w_reduce adds up in a
+// fixed order: deterministic.
 constexpr int kSlab = 256;
 
 template <int CIN, int CP, int COUT>
@@ -579,11 +584,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
     __shared__ float sR[4][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j = lane & 15, kq = lane >> 4;
+    const int qz = blockIdx.y;  // taps 9 qz .. 9 qz + 8 (dz = qz - 1)
     const int V = G * G * G, GG = G * G;
     const int ubase = 64 * kq + 16 * wave;  // this lane's product voxels: ubase + i
-    f4 acc[27];
+    f4 acc[9];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
     float accb = 0.f;  // bias of channel j from this lane's voxels
     const int nb = gridDim.x, per = (nslabs + nb - 1) / nb;
     const int s_lo = xcd_rank(blockIdx.x, nb) * per;
@@ -602,15 +608,16 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
             uy[i] = (vv / G) % G;
             uz[i] = vv / GG;
         }
-        auto fetch = [&](int t, f4 *R) {
-            const int dx = d * (t % 3 - 1), dy = d * ((t / 3) % 3 - 1), dz = d * (t / 9 - 1);
+        auto fetch = [&](int t9, f4 *R) {
+            const int dx = d * (t9 % 3 - 1), dy = d * (t9 / 3 - 1), dz = d * (qz - 1);
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 const int f = tid + 256 * i;
                 const int xx = ux[i] + dx, yy = uy[i] + dy, zz = uz[i] + dz;
-                R[i] = f4{0.f, 0.f, 0.f, 0.f};
-                if (uval[i] && xx >= 0 && xx < G && yy >= 0 && yy < G && zz >= 0 && zz < G)
-                    R[i] = *reinterpret_cast<const f4 *>(in + ((int64_t)(zz * G + yy) * G + xx) * CP + 4 * (f % QV));
+                const bool ok = uval[i] && xx >= 0 && xx < G && yy >= 0 && yy < G && zz >= 0 && zz < G;
+                const f4 val =
+                    *reinterpret_cast<const f4 *>(in + (ok ? ((int64_t)(zz * G + yy) * G + xx) * CP + 4 * (f % QV) : 0));
+                R[i] = ok ? val : f4{0.f, 0.f, 0.f, 0.f};
             }
         };
         f4 R0[NF], R1[NF];  // taps t and t + 1 in flight
@@ -620,12 +627,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int vg = v0 + ubase + i;
-            a[i] = (j < COUT && vg < V) ? g[(int64_t)vg * COUT + (COUT == 16 ? j : 0)] : 0.f;
+            const bool ok = j < COUT && vg < V;
+            const float val = g[ok ? (int64_t)vg * COUT + (COUT == 16 ? j : 0) : 0];
+            a[i] = ok ? val : 0.f;
             accb += a[i];
         }
         __syncthreads();  // the previous slab's products have read both buffers
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
+        for (int t = 0; t < 9; ++t) {
             float *T = sT[t & 1];
             f4 *R = (t & 1) ? R1 : R0;
 #pragma unroll
@@ -635,7 +644,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
                 for (int e = 0; e < 4; ++e) T[(c0 + e) * LD + u] = R[i][e];
             }
             __syncthreads();
-            if (t + 2 < 27) fetch(t + 2, R);
+            if (t + 2 < 9) fetch(t + 2, R);
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 f4 b = f4{0.f, 0.f, 0.f, 0.f};
@@ -649,22 +658,24 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w_mx(const float *__restrict__
     // block sums in a fixed order
     float *pb = part + (int64_t)blockIdx.x * COUT * CIN * 28;
 #pragma unroll
-    for (int t = 0; t < 27; ++t) {
+    for (int t = 0; t < 9; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) sR[wave][lane * 4 + r] = acc[t][r];
         __syncthreads();
         {
             const int i = tid, ln = i >> 2, c = 4 * (ln >> 4) + (i & 3), ci = ln & 15;
             const float s = (sR[0][i] + sR[1][i]) + (sR[2][i] + sR[3][i]);
-            if (c < COUT && ci < CIN) pb[(c * CIN + ci) * 28 + t] = s;
+            if (c < COUT && ci < CIN) pb[(c * CIN + ci) * 28 + 9 * qz + t] = s;
         }
         __syncthreads();
     }
-    accb += __shfl_xor(accb, 16, 64);
-    accb += __shfl_xor(accb, 32, 64);
-    if (kq == 0) sR[wave][j] = accb;
-    __syncthreads();
-    if (tid < COUT) pb[(tid * CIN + 0) * 28 + 27] = (sR[0][tid] + sR[1][tid]) + (sR[2][tid] + sR[3][tid]);
+    if (qz == 0) {  // the bias once per chunk
+        accb += __shfl_xor(accb, 16, 64);
+        accb += __shfl_xor(accb, 32, 64);
+        if (kq == 0) sR[wave][j] = accb;
+        __syncthreads();
+        if (tid < COUT) pb[(tid * CIN + 0) * 28 + 27] = (sR[0][tid] + sR[1][tid]) + (sR[2][tid] + sR[3][tid]);
+    }
 }
 
 int grid1(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65535); }
@@ -718,7 +729,7 @@ int bwd_w(const float *g, const float *in, float *part, int G, int d, float *gW,
     const int64_t V = (int64_t)G * G * G;
     const int nslabs = (int)((V + kSlab - 1) / kSlab);
     const int nch = mx_blocks(nslabs, 2, kWgBlocks);
-    hipLaunchKernelGGL((k_conv_bwd_w_mx<CIN, CP, COUT>), dim3(nch), dim3(256), 0, st, g, in, part, G, d, nslabs);
+    hipLaunchKernelGGL((k_conv_bwd_w_mx<CIN, CP, COUT>), dim3(nch, 3), dim3(256), 0, st, g, in, part, G, d, nslabs);
     const int tot = COUT * CIN * 27 + COUT;
     hipLaunchKernelGGL(k_conv_w_reduce, dim3((tot + 31) / 32), dim3(256), 0, st, part, nch, CIN, COUT, gW, gb);
     BF_HIP(hipGetLastError());
