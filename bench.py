@@ -719,7 +719,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "nodes": cube.m, "grid": 128,
                    "pad": 256, "edge_points": 100, "occupied_planes": info["z_count"],
-                   "z_schedule": info["zsched"], "autotune_us": info["tune_us"]},
+                   "z_schedule": info["zsched"], "autotune_us": info["tune_us"],
+                   "forward_kx_per_thread": info["fwd_xg"], "autotune_forward_us": info["fwd_tune_us"]},
         # the dominant kernel is the z pass; achieved = the model's z-pass bytes
         # (F g + K Hx Hy Hz b + O g) over its mean event time
         "roofline": {"bound": "hbm", "kernel": "k_zpass", "achieved": zroof["achieved"], "peak": HBM_PEAK_GBS,

@@ -129,9 +129,12 @@ typedef struct {
     int autotune;               /* radix schedule of the z transform: 0 the
                                    default one for the family, precision and
                                    length, 1 time every compiled schedule on
-                                   this plan and keep the fastest (cached per
-                                   kernel/precision/padded size in the file
-                                   named by BEMFFT_TUNE_CACHE, if set),
+                                   this plan and keep the fastest, then time
+                                   1 and 2 kx per thread in the forward
+                                   direct DFT and keep the faster (both
+                                   cached per kernel/precision/padded size in
+                                   the file named by BEMFFT_TUNE_CACHE, if
+                                   set),
                                    2 + s schedule s: 0 and 1 (16 or 32 lanes
                                    per pencil, by length) always exist; 2,
                                    the wide one with 64 lanes per pencil,
@@ -384,6 +387,11 @@ typedef struct {
                                     (0, 1 or 2)                               */
     double tune_us[3];           /* autotune: mean apply time per schedule, us
                                     (0 for schedules not timed)               */
+    int fwd_xg;                  /* kx per thread in the forward direct DFT
+                                    (1 or 2): from the row lengths, or timed
+                                    by autotune = 1                           */
+    double fwd_tune_us[2];       /* autotune = 1: mean apply time with 1 and 2
+                                    kx per thread, us (0 if not timed)        */
 } bemfft_plan_info;
 
 int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info);

@@ -51,7 +51,8 @@ class bemfft_plan_info(ctypes.Structure):
                 ("z_count", ctypes.c_int64), ("nfields", ctypes.c_int64), ("nspectra", ctypes.c_int64),
                 ("noutputs", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("spectra_bytes", ctypes.c_int64), ("spectrum_parity_residual", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double), ("zsched", ctypes.c_int), ("tune_us", ctypes.c_double * 3)]
+                ("plan_seconds", ctypes.c_double), ("zsched", ctypes.c_int), ("tune_us", ctypes.c_double * 3),
+                ("fwd_xg", ctypes.c_int), ("fwd_tune_us", ctypes.c_double * 2)]
 
 
 EXPORTS = [

@@ -550,9 +550,11 @@ int plan_create_impl(bemfft_plan *p, const bemfft_grid *grid, int64_t m, const d
     return 0;
 }
 
+// Cache entries hold zsched + 4 (fwd_xg - 1); the "2:" prefix keeps entries
+// written before the forward width was tuned (z schedule only) from being read.
 std::string tune_key(const bemfft_plan *p) {
-    return std::to_string(p->kernel) + ":" + std::to_string(p->eng.precision) + ":" + std::to_string(p->P[0]) + "x" +
-           std::to_string(p->P[1]) + "x" + std::to_string(p->P[2]);
+    return "2:" + std::to_string(p->kernel) + ":" + std::to_string(p->eng.precision) + ":" + std::to_string(p->P[0]) +
+           "x" + std::to_string(p->P[1]) + "x" + std::to_string(p->P[2]);
 }
 
 // Compiled z schedules of a plan: the default and the alternative one, and
@@ -605,13 +607,15 @@ void tune_cache_store(const std::string &key, int v) {
 }
 
 // Time the working-precision apply with each compiled z schedule and keep
-// the faster one.
+// the fastest, then, with that schedule, 1 and 2 kx per thread in the
+// forward direct DFT and keep the faster.
 int autotune_zsched(bemfft_plan *p, hipStream_t st) {
     const std::string key = tune_key(p);
     const int nsched = num_zsched(p);
     const int cached = tune_cache_lookup(key);
-    if (cached >= 0 && cached < nsched) {
-        p->zsched = cached;
+    if (cached >= 0 && cached % 4 < nsched && cached / 4 < 2) {
+        p->zsched = cached % 4;
+        p->fwd_xg = cached / 4 + 1;
         return 0;
     }
     const size_t bytes = (size_t)p->ncomp * p->m * sizeof(double);
@@ -631,17 +635,30 @@ int autotune_zsched(bemfft_plan *p, hipStream_t st) {
         hipEventCreate(&e1) != hipSuccess)
         status = BEMFFT_EDEVICE;
     const int reps = 20;
-    for (int sched = 0; sched < nsched && status == 0; ++sched) {
-        p->zsched = sched;
+    // mean apply time in us with the plan's current settings
+    auto time_apply = [&](double *us) {
         for (int i = 0; i < 3 && status == 0; ++i) status = launch_apply(p, p->eng, q, u, r, st);
-        if (status) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { status = BEMFFT_EDEVICE; break; }
+        if (status) return;
+        if (hipEventRecord(e0, st) != hipSuccess) { status = BEMFFT_EDEVICE; return; }
         for (int i = 0; i < reps && status == 0; ++i) status = launch_apply(p, p->eng, q, u, r, st);
         float ms = 0.f;
         if (status == 0 && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
             status = BEMFFT_EDEVICE;
-        p->tune_us[sched] = 1e3 * ms / reps;
+        *us = 1e3 * ms / reps;
+    };
+    for (int sched = 0; sched < nsched && status == 0; ++sched) {
+        p->zsched = sched;
+        time_apply(&p->tune_us[sched]);
+    }
+    if (status == 0) {
+        p->zsched = 0;
+        for (int sched = 1; sched < nsched; ++sched)
+            if (p->tune_us[sched] < p->tune_us[p->zsched]) p->zsched = sched;
+    }
+    for (int xg = 1; xg <= 2 && status == 0; ++xg) {
+        p->fwd_xg = xg;
+        time_apply(&p->fwd_tune_us[xg - 1]);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -652,10 +669,8 @@ int autotune_zsched(bemfft_plan *p, hipStream_t st) {
         if (status == BEMFFT_EDEVICE) set_error("autotune: HIP failure");
         return status;
     }
-    p->zsched = 0;
-    for (int sched = 1; sched < nsched; ++sched)
-        if (p->tune_us[sched] < p->tune_us[p->zsched]) p->zsched = sched;
-    tune_cache_store(key, p->zsched);
+    p->fwd_xg = p->fwd_tune_us[1] < p->fwd_tune_us[0] ? 2 : 1;
+    tune_cache_store(key, p->zsched + 4 * (p->fwd_xg - 1));
     return 0;
 }
 
@@ -769,6 +784,8 @@ int bemfft_plan_get_info(const bemfft_plan *p, bemfft_plan_info *info) {
     info->plan_seconds = p->plan_seconds;
     info->zsched = p->zsched;
     for (int i = 0; i < 3; ++i) info->tune_us[i] = p->tune_us[i];
+    info->fwd_xg = p->fwd_xg;
+    for (int i = 0; i < 2; ++i) info->fwd_tune_us[i] = p->fwd_tune_us[i];
     return 0;
 }
 

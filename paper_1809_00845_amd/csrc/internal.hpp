@@ -101,6 +101,7 @@ struct bemfft_plan {
     int zsched = 0;               // radix schedule of the z transform
     int cell_quad = 0;            // kernel values at m != 0: 0 point, q >= 2 cell mean (q^dim points)
     double tune_us[3] = {0, 0, 0};
+    double fwd_tune_us[2] = {0, 0};  // autotune: apply time with 1 and 2 kx per forward thread, us
     double plan_seconds = 0.0;
     // solve workspace, allocated on first use
     double *s_V = nullptr;

@@ -475,6 +475,28 @@ def test_autotune_picks_a_schedule(dev):
         assert all(x > 0 for x in t[:ns]) and all(x == 0 for x in t[ns:])
         assert info["zsched"] in range(ns)
         assert t[info["zsched"]] == min(t[:ns])
+        # then the forward pass's kx per thread, timed with the chosen schedule
+        f = list(info["fwd_tune_us"])
+        assert all(x > 0 for x in f) and info["fwd_xg"] in (1, 2)
+        assert f[info["fwd_xg"] - 1] == min(f)
+
+
+def test_autotuned_forward_width_matches_oracle(dev):
+    # both forward widths give the operator of the oracle: the plan with the
+    # autotuned width against the oracle, and the untuned plan (width from the
+    # row lengths) against the tuned one
+    g = I.sphere3d(24, 0.35)
+    rng = np.random.default_rng(11)
+    q, u = rng.uniform(-1, 1, g.m), rng.uniform(-1, 1, g.m)
+    outs = {}
+    for tune in (0, 1):
+        plan = B.Plan(g, B.LAPLACE3D, precision=B.FP64, autotune=tune)
+        outs[tune] = plan.apply(_t(q, dev), _t(u, dev)).cpu().numpy()
+        outs[("xg", tune)] = plan.info()["fwd_xg"]
+        plan.close()
+    ref, sc = O.apply(O.problem(g, O.LAPLACE3D), q, u, with_scale=True)
+    assert np.abs(outs[1] - ref).max() / np.max(sc) < 1e-12
+    assert np.abs(outs[0] - outs[1]).max() / np.max(sc) < 1e-13
 
 
 # ------------------------------------------------------------------ batches
