@@ -416,6 +416,7 @@ def bench_navier_star(B, I, dev, steps, mixed=True):
                     "apply_ms_median": median_apply_ms(pl, q, u, r, 50),
                     "stage_ms": dict(zip(names, st)),
                     "plan_seconds": inf["plan_seconds"],
+                    "z_schedule": inf["zsched"], "forward_kx_per_thread": inf["fwd_xg"],
                     "roofline": zpass_roofline(inf, b, st[1], kern),
                     "apply_model_bytes": sum(model_bytes(inf, b).values())}
     out["roofline"] = out["fp32"]["roofline"]
