@@ -179,6 +179,44 @@ def test_net_gradients_match_oracle(dev, G, dil):
     net.close()
 
 
+def test_net_gradients_full_size_sampled(dev):
+    """Gradients on the bench's 96^3 grid (dilations 1, 2, 4, 8) for a loss
+    on eight target voxels (corners, faces, interior).  A target's output
+    depends only on inputs within 15 voxels of it, and so does every
+    activation on its gradient paths, so the oracle computes each target's
+    gradient exactly on the 31^3 window that holds it (shifted inwards at
+    the grid's edge, where the network zero-pads as the oracle does at the
+    window's edge); their sum must equal the GPU's full-grid gradient, whose
+    sums run over every voxel of the grid.  Bars as for the small grids."""
+    G, dil, R = 96, (1, 2, 4, 8), 15
+    W = 2 * R + 1
+    net = B.Net(G, dil, seed=6)
+    p = _rand_params(net, 41, scale=0.15)
+    x = _sparse_input(G, 42, frac=0.02)
+    pts = [(0, 0, 0), (G - 1, G - 1, G - 1), (0, 47, 95), (48, 48, 48), (10, 90, 30), (95, 3, 60), (33, 66, 7),
+           (70, 20, 85)]
+    vox = np.array([(c[0] * G + c[1]) * G + c[2] for c in pts], dtype=np.int32)
+    rng = np.random.default_rng(43)
+    tgt = rng.standard_normal(len(pts)).astype(np.float32)
+    wt = rng.uniform(0.5, 1.5, len(pts)).astype(np.float32)
+    L, g = net.gradients(torch.tensor(x, device=dev), torch.tensor(vox, device=dev), torch.tensor(tgt, device=dev),
+                         torch.tensor(wt, device=dev))
+    net.close()
+    x4 = x.astype(np.float64).reshape(6, G, G, G)
+    Lr, gr = 0.0, np.zeros_like(p)
+    for i, c in enumerate(pts):
+        st = [min(max(ci - R, 0), G - W) for ci in c]
+        crop = x4[:, st[0]:st[0] + W, st[1]:st[1] + W, st[2]:st[2] + W]
+        lv = ((c[0] - st[0]) * W + (c[1] - st[1])) * W + (c[2] - st[2])
+        Li, gi = NN.loss_and_grad(p, list(dil), crop, np.array([lv]), np.array([float(tgt[i])]),
+                                  np.array([float(wt[i])]))
+        Lr += Li
+        gr += gi
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    assert np.abs(g - gr).max() <= 2e-4 * np.abs(gr).max()
+    assert np.linalg.norm(g - gr) <= 2e-5 * np.linalg.norm(gr)
+
+
 def test_net_adam_steps_match_oracle(dev):
     G = 11
     net = B.Net(G, DIL, seed=4)
