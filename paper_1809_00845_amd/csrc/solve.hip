@@ -315,12 +315,23 @@ __global__ __launch_bounds__(256) void k_gemv_norm_r(const double *V, int64_t ld
     if (threadIdx.x == 0) pout[blockIdx.x] = (sm4[0] + sm4[1]) + (sm4[2] + sm4[3]);
 }
 
+// A step's last result for the host: the norm, then (if flag is given) the
+// step's sequence number with system-scope release -- everything the step
+// wrote for the host is visible once the host reads the flag.
+__device__ __forceinline__ void post_step(double *nout, double a, uint64_t *flag, uint64_t seq) {
+    *nout = a;
+    __threadfence_system();
+    if (flag) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ||w|| = sqrt(sum of the norm partials), then v = w / ||w|| stored as the
-// basis column and v * scale split into the unknown slots of (q, u); block
-// 0 writes ||w|| to nout if given
+// basis column and v * scale split into the unknown slots of (q, u).  Block
+// 0 posts the previous step's result if nout is given (pinned host memory):
+// ||w|| to nout, then seq to flag with system-scope release, as k_norm_r
+// does (the same sum in the same order).
 __global__ __launch_bounds__(256) void k_split_norm_r(const uint8_t *bc, const double *w, const double *pnorm, int nblk,
                                                       const double *scale, double *v_out, double *q, double *u,
-                                                      int64_t n, double *nout) {
+                                                      int64_t n, double *nout, uint64_t *flag, uint64_t seq) {
     __shared__ double nrm[1];
     if (threadIdx.x < 64) {
         double s = 0.0;
@@ -331,10 +342,7 @@ __global__ __launch_bounds__(256) void k_split_norm_r(const uint8_t *bc, const d
     }
     __syncthreads();
     const double a = nrm[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && nout) {  // pinned host memory
-        *nout = a;
-        __threadfence_system();
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nout) post_step(nout, a, flag, seq);
     const double inv = a > 0.0 ? 1.0 / a : 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double v = w[i] * inv;
@@ -350,7 +358,8 @@ __global__ __launch_bounds__(256) void k_split_norm_r(const uint8_t *bc, const d
 // The basis column v = w / ||w|| is the same, bit for bit.
 __global__ __launch_bounds__(256) void k_split_norm_blk(const uint8_t *bc, const double *w, const double *pnorm,
                                                         int nblk, const double *blk, double *v_out, double *q,
-                                                        double *u, int64_t m) {
+                                                        double *u, int64_t m, double *nout, uint64_t *flag,
+                                                        uint64_t seq) {
     __shared__ double nrm[1];
     if (threadIdx.x < 64) {
         double s = 0.0;
@@ -361,6 +370,7 @@ __global__ __launch_bounds__(256) void k_split_norm_blk(const uint8_t *bc, const
     }
     __syncthreads();
     const double a = nrm[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nout) post_step(nout, a, flag, seq);
     const double inv = a > 0.0 ? 1.0 / a : 0.0;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
         double v[3];
@@ -383,11 +393,7 @@ __global__ __launch_bounds__(64) void k_norm_r(const double *pnorm, int nblk, do
     for (int b = threadIdx.x; b < nblk; b += 64) s += pnorm[b];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (threadIdx.x == 0) {  // out may be pinned host memory
-        *out = sqrt(s);
-        __threadfence_system();
-        if (flag) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    if (threadIdx.x == 0) post_step(out, sqrt(s), flag, seq);  // out may be pinned host memory
 }
 
 // Host side: wait until the device has stored seq at flag (pinned memory).
@@ -586,6 +592,11 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
         auto step_seq = [&](int kk) { return seq0 + (uint64_t)kk + 1; };
         const int gc = std::min(kConsumer, grid_for(n));
         auto col_of = [&](int kk) { return pipelined ? hp + 1024 * (kk & 1) : ws.hd; };
+        const int kmax = std::min(mcap, maxit - iters);
+        // Pipelined, every step but the last of the cycle has its norm and
+        // completion flag posted by the next step's first kernel, which sums
+        // the same norm partials in the same order (one kernel less per step);
+        // the last step, and every step when unpipelined, posts its own.
         auto queue_step = [&](int kk) -> int {
             double *vk = ws.V + (int64_t)kk * n;
             double *hc = col_of(kk);
@@ -600,12 +611,14 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
                     BF_CHECK(apply_unknown(p, e, bc, vk, ws.dinv, ws, ws.w, st));
                 }
             } else {
+                double *pn = pipelined ? col_of(kk - 1) + 512 + kk : nullptr;  // step kk - 1's ||w||
+                uint64_t *pf = pipelined ? reinterpret_cast<uint64_t *>(col_of(kk - 1) + 1023) : nullptr;
                 if (ws.blkmode)
                     hipLaunchKernelGGL(k_split_norm_blk, dim3(grid_for(m)), dim3(256), 0, st, bc, ws.w, red3, gc,
-                                       ws.blk, vk, ws.q, ws.u, m);
+                                       ws.blk, vk, ws.q, ws.u, m, pn, pf, step_seq(kk - 1));
                 else
                     hipLaunchKernelGGL(k_split_norm_r, dim3(grid_for(n)), dim3(256), 0, st, bc, ws.w, red3, gc, ws.dinv,
-                                       vk, ws.q, ws.u, n, (double *)nullptr);
+                                       vk, ws.q, ws.u, n, pn, pf, step_seq(kk - 1));
                 BF_HIP(hipGetLastError());
                 BF_CHECK(launch_apply(p, e, ws.q, ws.u, ws.w, st));
             }
@@ -617,13 +630,14 @@ int gmres_core(bemfft_plan *p, const Engine &e, const uint8_t *bc, const double 
                                ws.w, n, red2);
             hipLaunchKernelGGL(k_gemv_norm_r, dim3(gc), dim3(256), 0, st, ws.V, n, kk + 1, red2, ws.w, n, hc + 512,
                                red3);
-            uint64_t *flag = pipelined ? reinterpret_cast<uint64_t *>(hc + 1023) : nullptr;
-            hipLaunchKernelGGL(k_norm_r, dim3(1), dim3(64), 0, st, red3, gc, hc + 512 + kk + 1, flag, step_seq(kk));
+            if (!pipelined || kk + 1 >= kmax) {
+                uint64_t *flag = pipelined ? reinterpret_cast<uint64_t *>(hc + 1023) : nullptr;
+                hipLaunchKernelGGL(k_norm_r, dim3(1), dim3(64), 0, st, red3, gc, hc + 512 + kk + 1, flag, step_seq(kk));
+            }
             BF_HIP(hipGetLastError());
             if (!pipelined) BF_HIP(hipMemcpyAsync(hp, ws.hd, 1024 * sizeof(double), hipMemcpyDeviceToHost, st));
             return 0;
         };
-        const int kmax = std::min(mcap, maxit - iters);
         if (pipelined) BF_CHECK(queue_step(0));
         for (; k < kmax; ++k) {
             if (pipelined) {
