@@ -607,8 +607,8 @@ void tune_cache_store(const std::string &key, int v) {
 }
 
 // Time the working-precision apply with each compiled z schedule and keep
-// the fastest, then, with that schedule, 1 and 2 kx per thread in the
-// forward direct DFT and keep the faster.
+// the fastest, then, with that schedule, the other number of kx per thread
+// in the forward direct DFT (1 or 2) and keep the faster.
 int autotune_zsched(bemfft_plan *p, hipStream_t st) {
     const std::string key = tune_key(p);
     const int nsched = num_zsched(p);
@@ -656,9 +656,13 @@ int autotune_zsched(bemfft_plan *p, hipStream_t st) {
         for (int sched = 1; sched < nsched; ++sched)
             if (p->tune_us[sched] < p->tune_us[p->zsched]) p->zsched = sched;
     }
-    for (int xg = 1; xg <= 2 && status == 0; ++xg) {
-        p->fwd_xg = xg;
-        time_apply(&p->fwd_tune_us[xg - 1]);
+    // the width in use was timed with every schedule above; only the other one
+    // needs applies of its own
+    if (status == 0) {
+        const int xg0 = p->fwd_xg, xg1 = 3 - xg0;
+        p->fwd_tune_us[xg0 - 1] = p->tune_us[p->zsched];
+        p->fwd_xg = xg1;
+        time_apply(&p->fwd_tune_us[xg1 - 1]);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
