@@ -823,31 +823,29 @@ __device__ __forceinline__ void gather_body(const ApplyArgs &a, const int bx) {
     const int step = (L * xg) % px;
     int idx = ((1 + sub) * xg) % px;  // (kx x) mod px
     int kx = 1 + sub;
-    // four coefficients per output in flight before they are used
-    for (; kx + 3 * L < hx - 1; kx += 4 * L) {
-        cx<R> v[4][O];
+    // eight coefficients per output in flight before they are used.  Past
+    // the row's end a lane loads kx = 1 (in bounds: the loop runs only when
+    // hx >= 3) and weighs it by zero -- a product, so the load stays
+    // unconditional and the chunk's loads are waited for together.
+    for (; kx < hx - 1; kx += 8 * L) {
+        cx<R> v[8][O];
+        R mk[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 8; ++k) {
+            const bool in = kx + k * L < hx - 1;
+            const int kc = in ? kx + k * L : 1;
+            mk[k] = in ? R(1) : R(0);
 #pragma unroll
-            for (int o = 0; o < O; ++o) v[k][o] = row[o * rstride + kx + k * L];
+            for (int o = 0; o < O; ++o) v[k][o] = row[o * rstride + kc];
+        }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {
             const cx<R> w = twx[idx];
 #pragma unroll
-            for (int o = 0; o < O; ++o) acc[o] += (double)(v[k][o].x * w.x + v[k][o].y * w.y);
+            for (int o = 0; o < O; ++o) acc[o] += (double)((v[k][o].x * w.x + v[k][o].y * w.y) * mk[k]);
             idx += step;
             if (idx >= px) idx -= px;
         }
-    }
-    for (; kx < hx - 1; kx += L) {
-        const cx<R> w = twx[idx];
-#pragma unroll
-        for (int o = 0; o < O; ++o) {
-            const cx<R> v = row[o * rstride + kx];
-            acc[o] += (double)(v.x * w.x + v.y * w.y);
-        }
-        idx += step;
-        if (idx >= px) idx -= px;
     }
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1)
