@@ -159,23 +159,36 @@ __global__ __launch_bounds__(256) void kb_fields(const ApplyArgs *members, const
     fields_body<R, KIND>(a, blockIdx.x, blockIdx.y, blockIdx.z % zdiv);
 }
 
-// Value of field f at sorted node s, computed from q and u exactly as
-// fields_body stores it (same operations, same rounding), for kernels that
-// must not wait for k_fields.
+// All F field values of sorted node s at once (one set of loads), computed
+// from q and u exactly as fields_body stores them (same operations, same
+// rounding), for the long-row transforms, which do not wait for k_fields.
 template <typename R, int KIND>
-__device__ __forceinline__ R field_value(const ApplyArgs &a, const int s, const int f) {
+__device__ __forceinline__ void node_fields(const ApplyArgs &a, const int s, R *v) {
+    constexpr int F = Terms<KIND>::F;
     const int j = a.perm[s];
     const double wt = a.w[s];
-    if constexpr (KIND == 0 || KIND == 1) {
-        if (f == 0) return (R)(a.q[j] * wt);
+    if constexpr (KIND == 3) {  // half-space: the three traction components
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = (R)(a.q[c * a.m + j] * wt);
+    } else if constexpr (KIND == 0 || KIND == 1) {
+        v[0] = (R)(a.q[j] * wt);
         const double uw = a.u[j] * wt;
-        return (R)(uw * a.nrm[(f - 1) * a.m + s]);
+#pragma unroll
+        for (int f = 1; f < F; ++f) v[f] = (R)(uw * a.nrm[(f - 1) * a.m + s]);
     } else {
-        if (f < 3) return (R)(a.q[f * a.m + j] * wt);
-        const int p = f - 3, i = pair_i(p), k = pair_j(p);
-        const double ui = a.u[i * a.m + j], uk = a.u[k * a.m + j];
-        const double ni = a.nrm[i * a.m + s], nk = a.nrm[k * a.m + s];
-        return (R)((i == k ? ui * ni : ui * nk + uk * ni) * wt);
+        static_assert(F == 9, "Navier: three tractions and six symmetrised u n products");
+        double uu[3], nn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = (R)(a.q[c * a.m + j] * wt);
+            uu[c] = a.u[c * a.m + j];
+            nn[c] = a.nrm[c * a.m + s];
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = pair_i(p), k = pair_j(p);
+            v[3 + p] = (R)((i == k ? uu[i] * nn[i] : uu[i] * nn[k] + uu[k] * nn[i]) * wt);
+        }
     }
 }
 
@@ -210,6 +223,7 @@ __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, 
     const int pen = tid / TPP, t = tid % TPP;
     cx<R> *pb = buf + pen * PS;
     cx<R> *Xd = static_cast<cx<R> *>(a.Xd);
+#pragma unroll
     for (int f0 = 0; f0 < F; f0 += NPEN) {
 #pragma unroll
         for (int e = 0; e < E; ++e) pb[pslot(t + e * TPP)] = {R(0), R(0)};
@@ -217,12 +231,17 @@ __device__ __forceinline__ void rows_fft_body(const ApplyArgs &a, const int bx, 
         for (int s = s0 + tid; s < s1; s += 256) {
             const int x = a.gx[s];
             if (s > s0 && a.gx[s - 1] == x) continue;  // summed by the first node of the cell
-            for (int fl = 0; fl < NPEN && f0 + fl < F; ++fl) {
-                const int f = f0 + fl;
-                R v = field_value<R, KIND>(a, s, f);
-                for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) v += field_value<R, KIND>(a, s2, f);
-                buf[fl * PS + pslot(x)] = {v, R(0)};
+            R v[F];
+            node_fields<R, KIND>(a, s, v);  // all fields of the node from one set of loads
+            for (int s2 = s + 1; s2 < s1 && a.gx[s2] == x; ++s2) {
+                R v2[F];
+                node_fields<R, KIND>(a, s2, v2);
+#pragma unroll
+                for (int f = 0; f < F; ++f) v[f] += v2[f];
             }
+#pragma unroll
+            for (int fl = 0; fl < NPEN; ++fl)
+                if (f0 + fl < F) buf[fl * PS + pslot(x)] = {v[f0 + fl], R(0)};
         }
         __syncthreads();
         const int f = f0 + pen;
